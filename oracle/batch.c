@@ -1,0 +1,108 @@
+/*
+ * Batched drivers of the CPU oracle: an OpenMP loop over independent
+ * instances, each handled by the plain per-instance routines of oracle.c.
+ *
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check and the CPU-baseline leg of
+ * the benchmark).  Instances are column-major and stored one after another.
+ */
+#include <stddef.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+void orc_dsyrk_ln(int m, int k, double alpha, const double *A, int lda,
+                  const double *B, int ldb, double beta, const double *C,
+                  int ldc, double *D, int ldd);
+int orc_dpotrf_l(int m, const double *C, int ldc, double *D, int ldd,
+                 double *dA);
+void orc_dtrsm_rltn(int m, int n, double alpha, const double *L, int ldl,
+                    const double *B, int ldb, double *D, int ldd);
+void orc_dpotrs_l(int n, int nrhs, const double *L, int ldl, const double *B,
+                  int ldb, double *X, int ldx);
+int orc_ric_trf(int nx, int nu, int N, const double *A, int lda,
+                const double *B, int ldb, const double *Q, int ldq,
+                const double *R, int ldr, const double *PN, int ldp,
+                double *F);
+
+static int set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  int used = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    used = omp_get_num_threads();
+  }
+  return used;
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+/* Uniform batch of the range-space pair of §4.7.2: per instance
+ *   L = chol(Q + B*B^T)   (syrk_ln then potrf_l),
+ *   X = RHS * L^{-T}      (trsm_rltn),
+ * with Q n-by-n (lower read), B n-by-k, RHS nrhs-by-n.  Returns the number
+ * of threads used. */
+int orc_batch_syrk_potrf_trsm(int batch, int n, int k, int nrhs,
+                              const double *Q, const double *B,
+                              const double *RHS, double *L, double *X,
+                              double *dA, int *info, int nthreads) {
+  int used = set_threads(nthreads);
+  size_t sq = (size_t)n * n, sb = (size_t)n * k, sr = (size_t)nrhs * n;
+#pragma omp parallel
+  {
+    double *M = (double *)malloc(sizeof(double) * (sq > 0 ? sq : 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int b = 0; b < batch; ++b) {
+      orc_dsyrk_ln(n, k, 1.0, B + b * sb, n, B + b * sb, n, 1.0, Q + b * sq,
+                   n, M, n);
+      int inf = orc_dpotrf_l(n, M, n, L + b * sq, n, dA + (size_t)b * n);
+      info[b] = inf;
+      if (inf == 0)
+        orc_dtrsm_rltn(nrhs, n, 1.0, L + b * sq, n, RHS + b * sr, nrhs,
+                       X + b * sr, nrhs);
+    }
+    free(M);
+  }
+  return used;
+}
+
+/* Uneven batch of Cholesky solves: instance b has order n[b]; its matrix
+ * starts at A + offA[b] (column-major, lda = n[b]), its right-hand side at
+ * rhs + offv[b]; L, dA and x use the same offsets.  Returns the number of
+ * threads used. */
+int orc_batch_potrf_potrs(int batch, const int *n, const long long *offA,
+                          const long long *offv, const double *A,
+                          const double *rhs, double *L, double *dA,
+                          double *x, int *info, int nthreads) {
+  int used = set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b) {
+    int nb = n[b];
+    int inf = orc_dpotrf_l(nb, A + offA[b], nb, L + offA[b], nb, dA + offv[b]);
+    info[b] = inf;
+    if (inf == 0) orc_dpotrs_l(nb, 1, L + offA[b], nb, rhs + offv[b], nb,
+                               x + offv[b], nb);
+  }
+  return used;
+}
+
+/* Batch of backward Riccati recursions (§5.3), one problem per instance,
+ * all of the same sizes.  F receives N factors of order nu+nx per problem.
+ * Returns the number of threads used. */
+int orc_batch_ric_trf(int batch, int nx, int nu, int N, const double *A,
+                      const double *B, const double *Q, const double *R,
+                      const double *PN, double *F, int *info, int nthreads) {
+  int used = set_threads(nthreads);
+  size_t sa = (size_t)nx * nx, sbb = (size_t)nx * nu, sr = (size_t)nu * nu;
+  size_t sf = (size_t)N * (nu + nx) * (nu + nx);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b)
+    info[b] = orc_ric_trf(nx, nu, N, A + b * sa, nx, B + b * sbb, nx,
+                          Q + b * sa, nx, R + b * sr, nu, PN + b * sa, nx,
+                          F + b * sf);
+  return used;
+}

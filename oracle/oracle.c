@@ -1,0 +1,302 @@
+/*
+ * Plain CPU oracle for the panel-major dense linear algebra routines of
+ * "BLASFEO: basic linear algebra subroutines for embedded optimization"
+ * (Frison, Kouzoupis, Sartor, Zanelli, Diehl, arXiv 1704.02457).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links, loads or calls
+ * this file: only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or helper with the HIP path.
+ *
+ * Storage: every matrix here is plain column-major FP64 (element (i,j) at
+ * A[i + j*lda]), the format of the paper's reference implementation (§3.2),
+ * not the panel-major format of the high-performance implementation.  All
+ * loops are the textbook triple loops with the reduction index ascending;
+ * there is no blocking, fusion or reordering.  Build with
+ * `gcc -O2 -ffp-contract=off` so that no multiply-add is contracted.
+ *
+ * Each function states the passage of the paper it follows.  Readings of
+ * passages that are silent or ambiguous are listed in the design notes.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EL(A, lda, i, j) (A)[(size_t)(i) + (size_t)(j) * (size_t)(lda)]
+
+/* gemm_nt, Appendix A.2 (interface example): D <- alpha*A*B^T + beta*C with
+ * A m-by-k, B n-by-k, C and D m-by-n; C and D may be the same array. */
+void orc_dgemm_nt(int m, int n, int k, double alpha, const double *A, int lda,
+                  const double *B, int ldb, double beta, const double *C,
+                  int ldc, double *D, int ldd) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += EL(A, lda, i, l) * EL(B, ldb, j, l);
+      EL(D, ldd, i, j) = beta * EL(C, ldc, i, j) + alpha * s;
+    }
+}
+
+/* syrk_ln, §5.2.2 (syrk_ln paragraph): the lower triangle of
+ * alpha*A*B^T + beta*C, where the two factors A and B (both m-by-k) may
+ * differ.  The strictly upper part of D is neither read nor written. */
+void orc_dsyrk_ln(int m, int k, double alpha, const double *A, int lda,
+                  const double *B, int ldb, double beta, const double *C,
+                  int ldc, double *D, int ldd) {
+  for (int j = 0; j < m; ++j)
+    for (int i = j; i < m; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += EL(A, lda, i, l) * EL(B, ldb, j, l);
+      EL(D, ldd, i, j) = beta * EL(C, ldc, i, j) + alpha * s;
+    }
+}
+
+/* potrf_l, §5.2.2 (potrf_l paragraph) and §4.7.1 (inverse of the diagonal):
+ * the lower Cholesky factor L of the symmetric matrix whose lower triangle
+ * is C, so that L*L^T = C.  Column j of L follows from the definition
+ *   L[j][j] = sqrt(C[j][j] - sum_{k<j} L[j][k]^2),
+ *   L[i][j] = (C[i][j] - sum_{k<j} L[i][k]*L[j][k]) / L[j][j],  i > j,
+ * where the division is a multiplication by the reciprocal 1/L[j][j], which
+ * is also saved in dA[j] for later solves (§4.7.1).  Only the lower triangle
+ * of C is read; C and D may be the same array.  Returns 0, or j+1 for the
+ * first column whose pivot is not positive (LAPACK's info convention); the
+ * columns before it are complete. */
+int orc_dpotrf_l(int m, const double *C, int ldc, double *D, int ldd,
+                 double *dA) {
+  for (int j = 0; j < m; ++j) {
+    double d = EL(C, ldc, j, j);
+    for (int k = 0; k < j; ++k) d -= EL(D, ldd, j, k) * EL(D, ldd, j, k);
+    if (!(d > 0.0)) return j + 1;
+    double ljj = sqrt(d);
+    double inv = 1.0 / ljj;
+    EL(D, ldd, j, j) = ljj;
+    if (dA) dA[j] = inv;
+    for (int i = j + 1; i < m; ++i) {
+      double s = EL(C, ldc, i, j);
+      for (int k = 0; k < j; ++k) s -= EL(D, ldd, i, k) * EL(D, ldd, j, k);
+      EL(D, ldd, i, j) = s * inv;
+    }
+  }
+  return 0;
+}
+
+/* trsm_rltn, §5.2.2 (trsm paragraph) and §4.7.2 (the A*L^-T step of the
+ * range-space method): D = alpha * B * L^{-T} with L n-by-n lower triangular
+ * (not unit) and B m-by-n, i.e. the X that solves X*L^T = alpha*B.  Row i of
+ * X is found column by column,
+ *   X[i][j] = (alpha*B[i][j] - sum_{k<j} X[i][k]*L[j][k]) * (1/L[j][j]).
+ * Only the lower triangle of L is read.  B and D may be the same array. */
+void orc_dtrsm_rltn(int m, int n, double alpha, const double *L, int ldl,
+                    const double *B, int ldb, double *D, int ldd) {
+  for (int j = 0; j < n; ++j) {
+    double inv = 1.0 / EL(L, ldl, j, j);
+    for (int i = 0; i < m; ++i) {
+      double s = alpha * EL(B, ldb, i, j);
+      for (int k = 0; k < j; ++k) s -= EL(D, ldd, i, k) * EL(L, ldl, j, k);
+      EL(D, ldd, i, j) = s * inv;
+    }
+  }
+}
+
+/* syrk_potrf_ln, Appendix A.3 (LAPACK-like list) and §4.7.2 (concatenating
+ * updates and downdates): L = chol(C + A*B^T), lower.  The oracle simply
+ * runs syrk_ln (alpha = beta = 1) into a scratch matrix and then potrf_l;
+ * the fused kernel computes the same mathematical result. */
+int orc_dsyrk_dpotrf_ln(int m, int k, const double *A, int lda,
+                        const double *B, int ldb, const double *C, int ldc,
+                        double *D, int ldd, double *dA) {
+  double *M = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) *
+                               (size_t)(m > 0 ? m : 1));
+  if (!M) return -1;
+  orc_dsyrk_ln(m, k, 1.0, A, lda, B, ldb, 1.0, C, ldc, M, m);
+  int info = orc_dpotrf_l(m, M, m, D, ldd, dA);
+  free(M);
+  return info;
+}
+
+/* Cholesky solve with the lower factor L (trsv_lnn then trsv_ltn of the
+ * level-2 list in Appendix A.3): for each of the nrhs columns b of B,
+ * forward substitution L*y = b, then back substitution L^T*x = y.  Each
+ * division is a multiplication by 1/L[j][j], the saved inverse diagonal of
+ * §4.7.1. */
+void orc_dpotrs_l(int n, int nrhs, const double *L, int ldl, const double *B,
+                  int ldb, double *X, int ldx) {
+  for (int r = 0; r < nrhs; ++r) {
+    const double *b = B + (size_t)r * (size_t)ldb;
+    double *x = X + (size_t)r * (size_t)ldx;
+    for (int i = 0; i < n; ++i) {
+      double s = b[i];
+      for (int k = 0; k < i; ++k) s -= EL(L, ldl, i, k) * x[k];
+      x[i] = s * (1.0 / EL(L, ldl, i, i));
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int k = i + 1; k < n; ++k) s -= EL(L, ldl, k, i) * x[k];
+      x[i] = s * (1.0 / EL(L, ldl, i, i));
+    }
+  }
+}
+
+/* symv_l (level-2 list, Appendix A.3): z = alpha*A*x + beta*y with A
+ * symmetric and only its lower triangle read. */
+void orc_dsymv_l(int n, double alpha, const double *A, int lda,
+                 const double *x, double beta, const double *y, double *z) {
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double a = (k <= i) ? EL(A, lda, i, k) : EL(A, lda, k, i);
+      s += a * x[k];
+    }
+    z[i] = beta * y[i] + alpha * s;
+  }
+}
+
+/* Normwise backward error of an approximate solution x of A*x = b (A
+ * symmetric, lower triangle read), in the Rigal-Gaches form
+ *   eta = ||b - A*x||_inf / (||A||_inf * ||x||_inf + ||b||_inf).
+ * Not from the paper: it is the acceptance test of the mixed-precision
+ * solver. */
+double orc_berr(int n, const double *A, int lda, const double *x,
+                const double *b) {
+  double rmax = 0.0, anorm = 0.0, xmax = 0.0, bmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0, rowabs = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double a = (k <= i) ? EL(A, lda, i, k) : EL(A, lda, k, i);
+      s += a * x[k];
+      rowabs += fabs(a);
+    }
+    double r = fabs(b[i] - s);
+    if (r > rmax) rmax = r;
+    if (rowabs > anorm) anorm = rowabs;
+    if (fabs(x[i]) > xmax) xmax = fabs(x[i]);
+    if (fabs(b[i]) > bmax) bmax = fabs(b[i]);
+  }
+  double den = anorm * xmax + bmax;
+  return den > 0.0 ? rmax / den : rmax;
+}
+
+/* Backward Riccati recursion in square-root form, §5.3.  With the dynamics
+ * x+ = A x + B u (A nx-by-nx, B nx-by-nu), cost blocks Q (nx-by-nx), R
+ * (nu-by-nu), S = 0, and terminal P_N, for n = N-1 down to 0:
+ *   C   = [B^T; A^T] * Lc_{n+1}            (Lc_{n+1} lower, nx-by-nx)
+ *   M   = [[R, 0], [0, Q]] + C*C^T         (lower triangle)
+ *   F_n = chol(M) = [[Lambda_n, 0], [L_n, Lc_n]]
+ * with Lc_N = chol(P_N).  The product with the lower triangular Lc sums only
+ * over its nonzero entries.  F (N blocks of (nu+nx)^2, column-major, block n
+ * at F + n*(nu+nx)^2) receives the lower triangles of the factors.  Returns
+ * 0, or a nonzero code (1000*(stage+1) + pivot) if a factorization fails;
+ * stage N denotes chol(P_N). */
+int orc_ric_trf(int nx, int nu, int N, const double *A, int lda,
+                const double *B, int ldb, const double *Q, int ldq,
+                const double *R, int ldr, const double *PN, int ldp,
+                double *F) {
+  int nm = nu + nx;
+  double *Lc = (double *)calloc((size_t)nx * nx, sizeof(double));
+  double *C = (double *)calloc((size_t)nm * nx, sizeof(double));
+  double *M = (double *)calloc((size_t)nm * nm, sizeof(double));
+  if (!Lc || !C || !M) { free(Lc); free(C); free(M); return -1; }
+  int info = orc_dpotrf_l(nx, PN, ldp, Lc, nx, NULL);
+  if (info) { free(Lc); free(C); free(M); return 1000 * (N + 1) + info; }
+  for (int n = N - 1; n >= 0; --n) {
+    /* C = [B^T; A^T] * Lc: row r < nu is column r of B, row nu+r is column
+     * r of A. */
+    for (int j = 0; j < nx; ++j)
+      for (int r = 0; r < nm; ++r) {
+        double s = 0.0;
+        for (int k = j; k < nx; ++k) {
+          double x = (r < nu) ? EL(B, ldb, k, r) : EL(A, lda, k, r - nu);
+          s += x * EL(Lc, nx, k, j);
+        }
+        EL(C, nm, r, j) = s;
+      }
+    /* M = blockdiag(R, Q) + C*C^T, lower triangle */
+    for (int j = 0; j < nm; ++j)
+      for (int i = j; i < nm; ++i) {
+        double base = 0.0;
+        if (i < nu && j < nu) base = EL(R, ldr, i, j);
+        else if (i >= nu && j >= nu) base = EL(Q, ldq, i - nu, j - nu);
+        double s = 0.0;
+        for (int k = 0; k < nx; ++k) s += EL(C, nm, i, k) * EL(C, nm, j, k);
+        EL(M, nm, i, j) = base + s;
+      }
+    double *Fn = F + (size_t)n * nm * nm;
+    info = orc_dpotrf_l(nm, M, nm, Fn, nm, NULL);
+    if (info) { free(Lc); free(C); free(M); return 1000 * (n + 1) + info; }
+    for (int j = 0; j < nx; ++j)
+      for (int i = j; i < nx; ++i) EL(Lc, nx, i, j) = EL(Fn, nm, nu + i, nu + j);
+  }
+  free(Lc); free(C); free(M);
+  return 0;
+}
+
+/* ---- single-precision pieces of the mixed-precision solve ----------------
+ * Not from the paper: the FP32 factor-and-solve that iterative refinement
+ * starts from.  Same definitions as orc_dpotrf_l / orc_dpotrs_l, with every
+ * operation in IEEE single precision. */
+int orc_spotrf_l(int m, const float *C, int ldc, float *D, int ldd) {
+  for (int j = 0; j < m; ++j) {
+    float d = EL(C, ldc, j, j);
+    for (int k = 0; k < j; ++k) d -= EL(D, ldd, j, k) * EL(D, ldd, j, k);
+    if (!(d > 0.0f)) return j + 1;
+    float ljj = sqrtf(d);
+    float inv = 1.0f / ljj;
+    EL(D, ldd, j, j) = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      float s = EL(C, ldc, i, j);
+      for (int k = 0; k < j; ++k) s -= EL(D, ldd, i, k) * EL(D, ldd, j, k);
+      EL(D, ldd, i, j) = s * inv;
+    }
+  }
+  return 0;
+}
+
+void orc_spotrs_l(int n, const float *L, int ldl, const float *b, float *x) {
+  for (int i = 0; i < n; ++i) {
+    float s = b[i];
+    for (int k = 0; k < i; ++k) s -= EL(L, ldl, i, k) * x[k];
+    x[i] = s * (1.0f / EL(L, ldl, i, i));
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    float s = x[i];
+    for (int k = i + 1; k < n; ++k) s -= EL(L, ldl, k, i) * x[k];
+    x[i] = s * (1.0f / EL(L, ldl, i, i));
+  }
+}
+
+/* Mixed-precision solve with FP64 iterative refinement, for one right-hand
+ * side: factor fl32(A) in single precision, x0 = solve32(fl32(b)); then
+ * repeat r = b - A*x (FP64, lower triangle of A), stop if the backward
+ * error of x is <= tol, else d = solve32(fl32(r)) and x = x + d (FP64).
+ * Returns the number of refinement updates applied (>= 0), -1 if the
+ * single-precision factorization fails, or -2 if tol is not reached within
+ * max_iter updates.  eta_out receives the final backward error. */
+int orc_dposv_mixed(int n, const double *A, int lda, const double *b,
+                    double tol, int max_iter, double *x, double *eta_out) {
+  float *A32 = (float *)calloc((size_t)n * n + 1, sizeof(float));
+  float *L32 = (float *)malloc(sizeof(float) * (size_t)n * n);
+  float *v32 = (float *)malloc(sizeof(float) * (size_t)n);
+  float *d32 = (float *)malloc(sizeof(float) * (size_t)n);
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  int ret = 0;
+  if (!A32 || !L32 || !v32 || !d32 || !r) { ret = -3; goto done; }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) EL(A32, n, i, j) = (float)EL(A, lda, i, j);
+  if (orc_spotrf_l(n, A32, n, L32, n)) { ret = -1; goto done; }
+  for (int i = 0; i < n; ++i) v32[i] = (float)b[i];
+  orc_spotrs_l(n, L32, n, v32, d32);
+  for (int i = 0; i < n; ++i) x[i] = (double)d32[i];
+  for (int it = 0;; ++it) {
+    double eta = orc_berr(n, A, lda, x, b);
+    if (eta_out) *eta_out = eta;
+    if (eta <= tol) { ret = it; break; }
+    if (it >= max_iter) { ret = -2; break; }
+    orc_dsymv_l(n, -1.0, A, lda, x, 1.0, b, r);
+    for (int i = 0; i < n; ++i) v32[i] = (float)r[i];
+    orc_spotrs_l(n, L32, n, v32, d32);
+    for (int i = 0; i < n; ++i) x[i] += (double)d32[i];
+  }
+done:
+  free(A32); free(L32); free(v32); free(d32); free(r);
+  return ret;
+}

@@ -1,0 +1,387 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+hand-derived fixtures, closed forms, exact rational arithmetic on tiny inputs,
+50-digit decimal Cholesky, invariants and special cases.  CPU only."""
+import ctypes
+import os
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+def _read_fixture(name):
+    rows = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows.setdefault(key, []).append(vals)
+    return rows
+
+
+def _frac_mat(X):
+    return [[Fraction(float(v)) for v in row] for row in np.asarray(X)]
+
+
+# ----------------------------------------------------------------- gemm_nt
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 5, 2), (7, 4, 8), (8, 8, 8)])
+def test_gemm_nt_exact_rational_bound(m, n, k):
+    """Every entry lies within the standard dot-product bound of the exact
+    rational value of alpha*A*B^T + beta*C."""
+    rng = np.random.default_rng(100 + m * 31 + n * 7 + k)
+    A, B, C = rng.uniform(-1, 1, (m, k)), rng.uniform(-1, 1, (n, k)), rng.uniform(-1, 1, (m, n))
+    alpha, beta = 0.75, -1.25
+    D = oracle.dgemm_nt(A, B, C, alpha, beta)
+    Af, Bf, Cf = _frac_mat(A), _frac_mat(B), _frac_mat(C)
+    gam = (k + 2) * U / (1 - (k + 2) * U)
+    for i in range(m):
+        for j in range(n):
+            ex = Fraction(beta) * Cf[i][j] + Fraction(alpha) * sum(Af[i][l] * Bf[j][l] for l in range(k))
+            mag = abs(beta * C[i, j]) + abs(alpha) * sum(abs(A[i, l] * B[j, l]) for l in range(k))
+            assert abs(float(Fraction(D[i, j]) - ex)) <= gam * mag + 1e-300
+
+
+def test_gemm_nt_integers_exact():
+    rng = np.random.default_rng(5)
+    A = rng.integers(-9, 10, (6, 5)).astype(float)
+    B = rng.integers(-9, 10, (4, 5)).astype(float)
+    C = rng.integers(-9, 10, (6, 4)).astype(float)
+    D = oracle.dgemm_nt(A, B, C, 2.0, -3.0)
+    exp = [[-3 * int(C[i, j]) + 2 * sum(int(A[i, l]) * int(B[j, l]) for l in range(5)) for j in range(4)] for i in range(6)]
+    assert np.array_equal(D, np.array(exp, dtype=float))
+
+
+def test_gemm_nt_identity_right_factor():
+    """With B = I, D = A + C exactly (alpha = beta = 1)."""
+    rng = np.random.default_rng(6)
+    A, C = rng.standard_normal((9, 9)), rng.standard_normal((9, 9))
+    assert np.array_equal(oracle.dgemm_nt(A, np.eye(9), C), A + C)
+
+
+def test_gemm_nt_in_place_c_equals_d():
+    """C and D may coincide (Appendix A.2)."""
+    rng = np.random.default_rng(7)
+    A, B = rng.integers(-3, 4, (5, 3)).astype(float), rng.integers(-3, 4, (4, 3)).astype(float)
+    C = np.asfortranarray(rng.integers(-3, 4, (5, 4)).astype(float))
+    exp = C + A @ B.T
+    L = oracle.lib()
+    p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    Af, Bf = np.asfortranarray(A), np.asfortranarray(B)
+    L.orc_dgemm_nt(5, 4, 3, 1.0, p(Af), 5, p(Bf), 4, 1.0, p(C), 5, p(C), 5)
+    assert np.array_equal(C, exp)
+
+
+# ----------------------------------------------------------------- syrk_ln
+
+def test_syrk_ln_rational_and_upper_untouched():
+    rng = np.random.default_rng(8)
+    m, k = 7, 5
+    A, B, C = rng.uniform(-1, 1, (m, k)), rng.uniform(-1, 1, (m, k)), rng.uniform(-1, 1, (m, m))
+    Af, Bf, Cf = (np.asfortranarray(x) for x in (A, B, C))
+    D = np.full((m, m), 123.5, order="F")
+    p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    oracle.lib().orc_dsyrk_ln(m, k, 0.5, p(Af), m, p(Bf), m, 2.0, p(Cf), m, p(D), m)
+    gam = (k + 2) * U / (1 - (k + 2) * U)
+    for i in range(m):
+        for j in range(m):
+            if i < j:
+                assert D[i, j] == 123.5
+                continue
+            ex = 2 * Fraction(C[i, j]) + Fraction(0.5) * sum(Fraction(A[i, l]) * Fraction(B[j, l]) for l in range(k))
+            mag = 2 * abs(C[i, j]) + 0.5 * sum(abs(A[i, l] * B[j, l]) for l in range(k))
+            assert abs(float(Fraction(D[i, j]) - ex)) <= gam * mag
+
+
+def test_syrk_ln_two_different_factors():
+    """A and B may differ: the result is the lower part of C + A B^T, not of
+    C + A A^T or C + B A^T (catches a swapped operand)."""
+    A = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 6.0]])
+    B = np.array([[0.0, 1.0], [1.0, 0.0], [2.0, -1.0]])
+    C = np.zeros((3, 3))
+    D = oracle.dsyrk_ln(A, B, C)
+    exp = np.tril(A @ B.T)
+    assert np.array_equal(D, exp)
+    assert not np.array_equal(exp, np.tril(B @ A.T))
+
+
+# ----------------------------------------------------------------- potrf_l
+
+def test_potrf_golden_4x4():
+    g = _read_fixture("chol_4x4.txt")
+    L = np.array(g["L"], dtype=float)
+    A = np.array(g["A"], dtype=float)
+    dA = np.array(g["dA"][0], dtype=float)
+    assert np.array_equal(L @ L.T, A)  # the fixture is self-consistent
+    D, d, info = oracle.dpotrf_l(A)
+    assert info == 0
+    assert np.array_equal(D, L)
+    assert np.array_equal(d, dA)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 33, 64])
+def test_potrf_small_integer_exact(n):
+    L, A = synth.small_integer_factor(n, seed=n)
+    D, dA, info = oracle.dpotrf_l(A)
+    assert info == 0
+    assert np.array_equal(D, L)
+    assert np.array_equal(dA, 1.0 / np.diag(L))
+
+
+def test_potrf_reads_only_lower():
+    L, A = synth.small_integer_factor(12, seed=3)
+    A2 = A.copy()
+    A2[np.triu_indices(12, 1)] = np.nan
+    D, _, info = oracle.dpotrf_l(A2)
+    assert info == 0 and np.array_equal(D, L)
+
+
+def test_potrf_identity_and_diagonal():
+    D, dA, info = oracle.dpotrf_l(np.eye(7))
+    assert info == 0 and np.array_equal(D, np.eye(7)) and np.array_equal(dA, np.ones(7))
+    d = np.array([2.0, 3.0, 0.5, 7.0, 1e-3, 1e5])
+    D, dA, info = oracle.dpotrf_l(np.diag(d))
+    assert info == 0
+    assert np.array_equal(np.diag(D), np.sqrt(d))
+    assert np.array_equal(dA, 1.0 / np.sqrt(d))
+    assert np.count_nonzero(D - np.diag(np.diag(D))) == 0
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_potrf_decimal_50_digits(n):
+    """Cholesky in 50-digit decimal arithmetic agrees to ~n*u relative."""
+    getcontext().prec = 50
+    rng = np.random.default_rng(40 + n)
+    M = rng.uniform(-1, 1, (n, n))
+    A = M @ M.T + n * np.eye(n)
+    A = 0.5 * (A + A.T)
+    Ad = [[Decimal(float(A[i, j])) for j in range(n)] for i in range(n)]
+    Ld = [[Decimal(0)] * n for _ in range(n)]
+    for j in range(n):
+        s = Ad[j][j] - sum(Ld[j][k] * Ld[j][k] for k in range(j))
+        Ld[j][j] = s.sqrt()
+        for i in range(j + 1, n):
+            Ld[i][j] = (Ad[i][j] - sum(Ld[i][k] * Ld[j][k] for k in range(j))) / Ld[j][j]
+    Lref = np.array([[float(v) for v in row] for row in Ld])
+    D, _, info = oracle.dpotrf_l(A)
+    assert info == 0
+    assert np.linalg.norm(D - Lref) / np.linalg.norm(Lref) <= 4 * n * U
+
+
+def test_potrf_residual_and_numpy_crosscheck():
+    rng = np.random.default_rng(9)
+    n = 40
+    G = rng.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    D, _, info = oracle.dpotrf_l(A)
+    assert info == 0
+    assert np.linalg.norm(D @ D.T - A) / np.linalg.norm(A) <= 10 * n * U
+    assert np.allclose(D, np.linalg.cholesky(A), rtol=0, atol=1e-12)
+    assert np.all(np.diag(D) > 0) and np.count_nonzero(np.triu(D, 1)) == 0
+
+
+@pytest.mark.parametrize("bad", [0, 3, 9])
+def test_potrf_info_first_failing_pivot(bad):
+    L, A = synth.small_integer_factor(10, seed=21)
+    A = A.copy()
+    # make the pivot of column `bad` exactly zero: d_bad = A[bad,bad] - sum L[bad,k]^2 = 0
+    A[bad, bad] -= L[bad, bad] ** 2
+    D, _, info = oracle.dpotrf_l(A)
+    assert info == bad + 1
+    assert np.array_equal(D[:, :bad], L[:, :bad])
+    A[bad, bad] -= 1.0  # negative pivot
+    assert oracle.dpotrf_l(A)[2] == bad + 1
+
+
+# ----------------------------------------------------------------- trsm_rltn
+
+def test_trsm_rltn_integer_recovery():
+    L, _ = synth.small_integer_factor(11, seed=13)
+    rng = np.random.default_rng(14)
+    X = rng.integers(-5, 6, (6, 11)).astype(float)
+    B = X @ L.T
+    assert np.array_equal(oracle.dtrsm_rltn(L, B), X)
+    assert np.array_equal(oracle.dtrsm_rltn(L, 2.0 * B, alpha=0.5), X)
+
+
+def test_trsm_rltn_rational_tiny():
+    """Against exact rational forward substitution for a 3x3 lower L."""
+    rng = np.random.default_rng(15)
+    L = np.tril(rng.uniform(-1, 1, (3, 3))) + 2 * np.eye(3)
+    B = rng.uniform(-1, 1, (2, 3))
+    alpha = 1.5
+    Lf, Bf = _frac_mat(L), _frac_mat(B)
+    X = oracle.dtrsm_rltn(L, B, alpha)
+    for i in range(2):
+        x = []
+        for j in range(3):
+            x.append((Fraction(alpha) * Bf[i][j] - sum(x[k] * Lf[j][k] for k in range(j))) / Lf[j][j])
+        for j in range(3):
+            assert abs(float(Fraction(X[i, j]) - x[j])) <= 1e-15 * max(1.0, abs(float(x[j])))
+
+
+def test_trsm_rltn_reads_only_lower():
+    L, _ = synth.small_integer_factor(6, seed=16)
+    L2 = L.copy()
+    L2[np.triu_indices(6, 1)] = np.nan
+    X = np.arange(12.0).reshape(2, 6)
+    assert np.array_equal(oracle.dtrsm_rltn(L2, X @ L.T), X)
+
+
+# ----------------------------------------------------------------- syrk_potrf
+
+def test_syrk_potrf_exact():
+    L, LL = synth.small_integer_factor(20, seed=17)
+    rng = np.random.default_rng(18)
+    A = rng.integers(-2, 3, (20, 9)).astype(float)
+    B = rng.integers(-2, 3, (20, 9)).astype(float)
+    S = A @ B.T
+    C = LL - np.tril(S) - np.tril(S, -1).T  # lower part of C + A B^T equals L L^T
+    D, dA, info = oracle.dsyrk_dpotrf_ln(A, B, C)
+    assert info == 0 and np.array_equal(D, L) and np.array_equal(dA, 1.0 / np.diag(L))
+
+
+# ----------------------------------------------------------------- potrs / symv / berr
+
+def test_potrs_golden_and_exact():
+    g = _read_fixture("chol_4x4.txt")
+    L = np.array(g["L"], dtype=float)
+    A = np.array(g["A"], dtype=float)
+    x = np.array(g["x"][0], dtype=float)
+    b = np.array(g["b"][0], dtype=float)
+    assert np.array_equal(A @ x, b)
+    assert np.array_equal(oracle.dpotrs_l(L, b)[:, 0], x)
+    L2, _ = synth.small_integer_factor(30, seed=19)
+    X = np.random.default_rng(20).integers(-4, 5, (30, 3)).astype(float)
+    assert np.array_equal(oracle.dpotrs_l(L2, (L2 @ L2.T) @ X), X)
+
+
+def test_symv_and_berr_closed_forms():
+    g = _read_fixture("chol_4x4.txt")
+    A = np.array(g["A"], dtype=float)
+    x = np.array(g["x"][0], dtype=float)
+    b = np.array(g["b"][0], dtype=float)
+    Al = np.tril(A)  # only the lower triangle is read
+    assert np.array_equal(oracle.dsymv_l(Al, x, b, -1.0, 1.0), np.zeros(4))
+    assert oracle.berr(Al, x, b) == 0.0
+    # A = I, x = b + delta e_0: eta = delta / (||x||_inf + ||b||_inf)
+    bb = np.array([1.0, -2.0, 0.5])
+    xx = bb.copy()
+    xx[0] += 0.25
+    assert oracle.berr(np.eye(3), xx, bb) == pytest.approx(0.25 / (2.0 + 2.0), rel=1e-15)
+
+
+# ----------------------------------------------------------------- Riccati
+
+def test_riccati_scalar_golden():
+    g = _read_fixture("riccati_scalar.txt")
+    a, b, q, r, pn = (float(g[k][0][0]) for k in ("a", "b", "q", "r", "PN"))
+    N = int(g["N"][0][0])
+    F, info = oracle.ric_trf(np.array([[a]]), np.array([[b]]), np.array([[q]]), np.array([[r]]), np.array([[pn]]), N)
+    assert info == 0
+    for n_s, lam2, llam, pn_s in g["S"]:
+        n = int(n_s)
+        Fn = F[n]
+        assert Fn[0, 0] ** 2 == pytest.approx(float(Fraction(lam2)), rel=4 * U)
+        assert Fn[1, 0] * Fn[0, 0] == pytest.approx(float(Fraction(llam)), rel=8 * U)
+        assert Fn[1, 1] ** 2 == pytest.approx(float(Fraction(pn_s)), rel=16 * U)
+        assert Fn[0, 1] == 0.0
+    # stage 1 in closed form: Lambda = 2, L = 3, Lc = 2 (to a few ulps, since
+    # Lc_2 = sqrt(3) is rounded)
+    assert np.allclose(F[1], [[2.0, 0.0], [3.0, 2.0]], rtol=8 * U, atol=0)
+
+
+def test_riccati_closed_form_no_input():
+    """B = 0, A = I, Q = I, P_N = I: P_n = (N - n + 1) I, Lc_n = sqrt(N-n+1) I,
+    Lambda_n = chol(R), L_n = 0."""
+    nx, nu, N = 5, 3, 6
+    R = np.diag([0.25, 4.0, 1.0])
+    F, info = oracle.ric_trf(np.eye(nx), np.zeros((nx, nu)), np.eye(nx), R, np.eye(nx), N)
+    assert info == 0
+    for n in range(N):
+        assert np.array_equal(F[n][:nu, :nu], np.diag([0.5, 2.0, 1.0]))
+        assert np.count_nonzero(F[n][nu:, :nu]) == 0
+        # sqrt(k)^2 is rounded, so each stage may move the result by an ulp
+        Lc = F[n][nu:, nu:]
+        assert np.count_nonzero(Lc - np.diag(np.diag(Lc))) == 0
+        assert np.allclose(np.diag(Lc), np.sqrt(N - n + 1.0), rtol=4 * N * U, atol=0)
+
+
+def test_riccati_matches_classical_form():
+    """Square-root recursion vs the classical Riccati difference equation with
+    explicit P (numpy, independent algorithm)."""
+    d = synth.riccati_batch(2, seed=3, nx=6, nu=2)
+    for s in range(2):
+        A, B, Q, R, PN = (d[k][s] for k in ("A", "B", "Q", "R", "PN"))
+        N = 7
+        F, info = oracle.ric_trf(A, B, Q, R, PN, N)
+        assert info == 0
+        P = PN.copy()
+        nu = B.shape[1]
+        for n in range(N - 1, -1, -1):
+            S = R + B.T @ P @ B
+            K = np.linalg.solve(S, B.T @ P @ A)
+            Pn = Q + A.T @ P @ A - A.T @ P @ B @ K
+            Lc = F[n][nu:, nu:]
+            Lam = F[n][:nu, :nu]
+            assert np.allclose(Lc @ Lc.T, Pn, rtol=1e-12, atol=1e-12)
+            assert np.allclose(Lam @ Lam.T, S, rtol=1e-12, atol=1e-12)
+            P = 0.5 * (Pn + Pn.T)
+
+
+# ----------------------------------------------------------------- mixed precision
+
+def test_spotrf_small_integer_exact_in_fp32():
+    L, A = synth.small_integer_factor(24, seed=22)
+    D, info = oracle.spotrf_l(A.astype(np.float32))
+    assert info == 0 and np.array_equal(D.astype(float), L)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_dposv_mixed_reaches_fp64_backward_error(cond):
+    ns, mats, rhs = synth.conditioned_batch(1, cond, seed=4, sizes=[40])
+    A, b = mats[0], rhs[0][:, 0]
+    x, it, eta = oracle.dposv_mixed(A, b, tol=1e-12, max_iter=30)
+    assert it >= 0 and eta <= 1e-12
+    assert eta == oracle.berr(A, x, b)
+    xr = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-12 * cond * 40
+    if cond >= 1e4:
+        assert it >= 1  # FP32 alone cannot reach 1e-12
+
+
+def test_dposv_mixed_non_spd():
+    A = np.diag([1.0, -1.0, 2.0])
+    x, it, eta = oracle.dposv_mixed(A, np.ones(3))
+    assert it == -1
+
+
+# ----------------------------------------------------------------- batched drivers
+
+def test_batch_drivers_match_single():
+    d = synth.uniform_batch(5, n=20, k=12, nrhs=3)
+    L, X, dA, info, used = oracle.batch_syrk_potrf_trsm(d["Q"], d["B"], d["RHS"], nthreads=2)
+    assert used >= 1 and np.all(info == 0)
+    for b in range(5):
+        Lb, db, ib = oracle.dsyrk_dpotrf_ln(d["B"][b], d["B"][b], d["Q"][b])
+        assert np.array_equal(L[b], Lb) and np.array_equal(dA[b], db)
+        assert np.array_equal(X[b], oracle.dtrsm_rltn(Lb, d["RHS"][b]))
+    ns, mats, rhs = synth.uneven_batch(6, step=8, nmax=40)
+    Ls, xs, ds, info, _ = oracle.batch_potrf_potrs(mats, rhs, nthreads=2)
+    for i in range(6):
+        Li, di, ii = oracle.dpotrf_l(mats[i])
+        assert np.array_equal(Ls[i], Li) and np.array_equal(xs[i], oracle.dpotrs_l(Li, rhs[i])[:, 0])
+    r = synth.riccati_batch(3, nx=4, nu=2)
+    F, info, _ = oracle.batch_ric_trf(r["A"], r["B"], r["Q"], r["R"], r["PN"], 5, nthreads=2)
+    for b in range(3):
+        Fb, ib = oracle.ric_trf(r["A"][b], r["B"][b], r["Q"][b], r["R"][b], r["PN"][b], 5)
+        assert np.array_equal(F[b], Fb)
