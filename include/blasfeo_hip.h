@@ -1,0 +1,262 @@
+/*
+ * blasfeo_hip.h -- C ABI of an MI355X (gfx950) library of dense linear
+ * algebra routines for small and medium matrices stored in the panel-major
+ * format of "BLASFEO: basic linear algebra subroutines for embedded
+ * optimization" (Frison et al., arXiv 1704.02457).
+ *
+ * Conventions (all entry points):
+ *  - Matrices are described by a host-side struct blasfeo_dmat whose pointers
+ *    pA and dA are DEVICE pointers, and are addressed by the paper's operand
+ *    triple (sA, ai, aj): the working sub-matrix has its top-left element at
+ *    row ai, column aj (§3 and Appendix A.2).  Char options are part of the
+ *    routine name (Appendix A.2).
+ *  - Panel-major storage (§4.3): rows are grouped in panels of BLASFEO_HIP_PS
+ *    = 16 rows; inside a panel the storage is column-major with leading
+ *    dimension 16; panels are 16*cn doubles apart, so element (i, j) is at
+ *        pA[(i - i % 16) * cn + j * 16 + i % 16].
+ *    A panel column (16 doubles) is one 128-byte line.  ps is a compile-time
+ *    constant, as the paper requires for the shift/mask address arithmetic.
+ *  - The caller owns every byte of memory.  No compute routine allocates
+ *    (Appendix A.1.2); the only allocating calls are blasfeo_allocate_dmat /
+ *    blasfeo_allocate_dvec (hipMalloc) and plan creation (host memory and a
+ *    small device table).
+ *  - All compute routines are asynchronous on the stream set with
+ *    blasfeo_hip_set_stream (default: the null stream) or on the stream
+ *    argument of the batched entry points (a hipStream_t passed as void*).
+ *  - Routines are non-destructive: the output operand is a separate argument,
+ *    which may coincide with an input where stated (Appendix A.2).
+ *  - Single-instance routines return void, like the paper's API.  Argument
+ *    errors are detected on the host before any launch; the routine then
+ *    launches nothing and records the error, readable (and cleared) with
+ *    blasfeo_hip_get_last_error().  Batched entry points return that code
+ *    directly: 0 = success, -i = argument i invalid, > 0 = HIP error code.
+ *  - Numerical failure of a Cholesky factorization is reported per instance
+ *    in a device int array info: 0, or j+1 for the first column j (0-based,
+ *    relative to the sub-matrix) whose pivot is not positive (LAPACK's
+ *    convention).  Entries of that column and later ones are unspecified;
+ *    the other instances of a batch are unaffected.
+ *  - Thread safety: the stream setting and the last error are per host
+ *    thread.  Calls that overlap on one device in different streams are
+ *    independent unless their operands overlap.
+ */
+#ifndef BLASFEO_HIP_H
+#define BLASFEO_HIP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLASFEO_HIP_PS 16  /* panel height for double precision */
+
+/* Matrix handle (Appendix A.1.1).  pA, m, n and memsize are the paper's
+ * common members; cn (the panel length "sda" of §4.3) and dA (the inverse
+ * diagonal of §4.7.1) are the high-performance implementation's members;
+ * pm (number of panels) and use_dA (dA holds the inverse diagonal of the
+ * whole matrix, set by a factorization at (0,0)) are this library's.
+ *   pA:  device pointer, pm*16*cn doubles, panel-major.
+ *   dA:  device pointer, max(m,n) doubles (inverse diagonal).
+ *   memsize: bytes of the chunk addressed by the struct, a multiple of 256,
+ *        so consecutive chunks of memsize bytes stay aligned. */
+struct blasfeo_dmat {
+  double *pA;
+  double *dA;
+  int m;
+  int n;
+  int pm;
+  int cn;
+  int use_dA;
+  int memsize;
+};
+
+/* Vector handle (Appendix A.1.1): unit stride, device pointer pa. */
+struct blasfeo_dvec {
+  double *pa;
+  int m;
+  int pm;
+  int memsize;
+};
+
+/* ------------------------------------------------------------------------
+ * Memory (Appendix A.1.2)
+ * ---------------------------------------------------------------------- */
+
+/* Bytes needed by an m-by-n matrix: pm*16*cn*8 for the panels (cn = n
+ * rounded up to a multiple of 4, pm = ceil(m/16)) plus max(m,n)*8 for dA,
+ * rounded up to 256.  Returns -1 if m < 0, n < 0 or the size overflows. */
+int blasfeo_memsize_dmat(int m, int n);
+/* Bytes needed by a vector of m doubles, rounded up to 256. */
+int blasfeo_memsize_dvec(int m);
+
+/* Sets the members of *sA so that it describes an m-by-n matrix living in
+ * the device memory chunk `memory` (at least blasfeo_memsize_dmat(m,n)
+ * bytes, 256-byte aligned).  The memory is not touched (Appendix A.1.2).
+ * pA = memory, dA = memory + pm*16*cn doubles. */
+void blasfeo_create_dmat(int m, int n, struct blasfeo_dmat *sA, void *memory);
+void blasfeo_create_dvec(int m, struct blasfeo_dvec *sx, void *memory);
+
+/* hipMalloc-backed creation and release (Appendix A.1.2). */
+void blasfeo_allocate_dmat(int m, int n, struct blasfeo_dmat *sA);
+void blasfeo_free_dmat(struct blasfeo_dmat *sA);
+void blasfeo_allocate_dvec(int m, struct blasfeo_dvec *sx);
+void blasfeo_free_dvec(struct blasfeo_dvec *sx);
+
+/* Conversion between column-major device arrays and panel-major storage
+ * (the packing routines of Appendix A.3), on the current stream.
+ *   pack:   sB[bi:bi+m, bj:bj+n] = A (m-by-n, column-major, leading dim lda)
+ *   unpack: B (m-by-n, leading dim ldb) = sA[ai:ai+m, aj:aj+n]
+ * A and B are device pointers.  Elements outside the sub-matrix, including
+ * panel padding, are not written. */
+void blasfeo_pack_dmat(int m, int n, const double *A, int lda,
+                       struct blasfeo_dmat *sB, int bi, int bj);
+void blasfeo_unpack_dmat(int m, int n, struct blasfeo_dmat *sA, int ai,
+                         int aj, double *B, int ldb);
+void blasfeo_pack_dvec(int m, const double *x, struct blasfeo_dvec *sy,
+                       int yi);
+void blasfeo_unpack_dvec(int m, struct blasfeo_dvec *sx, int xi, double *y);
+
+/* ------------------------------------------------------------------------
+ * Single-instance routines (Appendix A.2, A.3).  Sizes first, then
+ * operands.  Every operand must lie inside its matrix: ai + rows <= m and
+ * aj + cols <= n of the struct.
+ * ---------------------------------------------------------------------- */
+
+/* gemm_nt (Appendix A.2): D <- alpha*A*B^T + beta*C, A m-by-k at (ai,aj),
+ * B n-by-k at (bi,bj), C and D m-by-n.  C and D may be the same matrix at
+ * the same offsets; any other overlap of D with an input is undefined. */
+void blasfeo_dgemm_nt(int m, int n, int k, double alpha,
+                      struct blasfeo_dmat *sA, int ai, int aj,
+                      struct blasfeo_dmat *sB, int bi, int bj, double beta,
+                      struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj);
+
+/* syrk_ln (§5.2.2): lower triangle of D <- alpha*A*B^T + beta*C, A and B
+ * m-by-k (they may differ), C and D m-by-m.  Only elements on or below the
+ * diagonal of the D sub-matrix are written and only those of C are read. */
+void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
+                      int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                      int bj, double beta, struct blasfeo_dmat *sC, int ci,
+                      int cj, struct blasfeo_dmat *sD, int di, int dj);
+
+/* trsm_rltn (§5.2.2, §4.7.2): D <- alpha * B * A^{-T}, A n-by-n lower
+ * triangular, not unit, at (ai,aj) (only its lower triangle is read; the
+ * reciprocals of its diagonal are formed by the routine); B and D m-by-n.
+ * B and D may be the same matrix at the same offsets. */
+void blasfeo_dtrsm_rltn(int m, int n, double alpha, struct blasfeo_dmat *sA,
+                        int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                        int bj, struct blasfeo_dmat *sD, int di, int dj);
+
+/* potrf_l (§5.2.2, §4.6, §4.7.1): lower Cholesky factor D of the m-by-m
+ * matrix whose lower triangle is C.  Writes the lower triangle of D and
+ * sD->dA[0..m-1] = 1/diag(D); sets sD->use_dA = (di == 0 && dj == 0).
+ * C and D may be the same matrix at the same offsets. */
+void blasfeo_dpotrf_l(int m, struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj);
+
+/* syrk_potrf_ln (Appendix A.3, §4.7.2): D = chol(C + A*B^T), lower, with
+ * A, B m-by-k, and sD->dA as in potrf_l; the product is never stored. */
+void blasfeo_dsyrk_dpotrf_ln(int m, int k, struct blasfeo_dmat *sA, int ai,
+                             int aj, struct blasfeo_dmat *sB, int bi,
+                             int bj, struct blasfeo_dmat *sC, int ci,
+                             int cj, struct blasfeo_dmat *sD, int di,
+                             int dj);
+
+/* Variants of potrf_l and syrk_potrf_ln that also write the failure code
+ * (see Conventions) to the device int *info (may be NULL). */
+void blasfeo_hip_dpotrf_l_info(int m, struct blasfeo_dmat *sC, int ci,
+                               int cj, struct blasfeo_dmat *sD, int di,
+                               int dj, int *info);
+void blasfeo_hip_dsyrk_dpotrf_ln_info(int m, int k, struct blasfeo_dmat *sA,
+                                      int ai, int aj,
+                                      struct blasfeo_dmat *sB, int bi,
+                                      int bj, struct blasfeo_dmat *sC,
+                                      int ci, int cj,
+                                      struct blasfeo_dmat *sD, int di,
+                                      int dj, int *info);
+
+/* ------------------------------------------------------------------------
+ * Library state
+ * ---------------------------------------------------------------------- */
+
+/* Stream used by the single-instance routines of the calling host thread
+ * (a hipStream_t; NULL = the null stream). */
+void blasfeo_hip_set_stream(void *stream);
+void *blasfeo_hip_get_stream(void);
+/* Returns and clears the calling thread's last error (0 = none). */
+int blasfeo_hip_get_last_error(void);
+/* Static description of an error code. */
+const char *blasfeo_hip_strerror(int code);
+/* Library version as major*10000 + minor*100 + patch. */
+int blasfeo_hip_version(void);
+
+/* ------------------------------------------------------------------------
+ * Uniform batches.  A uniform batch of matrices is `batch` consecutive
+ * memory chunks of memsize bytes, each laid out as by blasfeo_create_dmat
+ * (the paper's memsize guarantee keeps every chunk aligned).  The struct
+ * argument describes instance 0; instance b uses pA and dA advanced by
+ * b*memsize bytes.  Offsets (ai, aj) apply to every instance.  info is a
+ * device array of `batch` ints (may be NULL where no factorization runs).
+ * Returns 0, -i for an invalid argument i (nothing launched), or a HIP
+ * error code.
+ * ---------------------------------------------------------------------- */
+
+/* Packing of a uniform batch: instance b of the column-major source starts
+ * strideA doubles after instance b-1 (and of the destination, strideB). */
+int blasfeo_hip_pack_dmat_batched(int batch, int m, int n, const double *A,
+                                  int lda, long long strideA,
+                                  const struct blasfeo_dmat *sB, int bi,
+                                  int bj, void *stream);
+int blasfeo_hip_unpack_dmat_batched(int batch, int m, int n,
+                                    const struct blasfeo_dmat *sA, int ai,
+                                    int aj, double *B, int ldb,
+                                    long long strideB, void *stream);
+
+int blasfeo_hip_dgemm_nt_batched(int batch, int m, int n, int k,
+                                 double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream);
+
+int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream);
+
+int blasfeo_hip_dtrsm_rltn_batched(int batch, int m, int n, double alpha,
+                                   const struct blasfeo_dmat *sA, int ai,
+                                   int aj, const struct blasfeo_dmat *sB,
+                                   int bi, int bj,
+                                   const struct blasfeo_dmat *sD, int di,
+                                   int dj, void *stream);
+
+int blasfeo_hip_dpotrf_l_batched(int batch, int m,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, int *info, void *stream);
+
+/* The range-space pair of §4.7.2 as one persistent fused kernel: per
+ * instance b
+ *     L = chol(Q + A*A^T)         (syrk_ln fused with potrf_l)
+ *     X = E * L^{-T}              (trsm_rltn)
+ * with A m-by-k (the factor of the update; syrk with both factors equal),
+ * Q m-by-m (lower read), E nrhs-by-m, outputs L (lower written, its dA
+ * filled) and X nrhs-by-m.  All sub-matrices start at (0,0).  Limits:
+ * 1 <= m <= 64, 0 <= k, 0 <= nrhs <= 16.  X may be NULL when nrhs == 0. */
+int blasfeo_hip_dsyrk_dpotrf_trsm_batched(int batch, int m, int k, int nrhs,
+                                          const struct blasfeo_dmat *sA,
+                                          const struct blasfeo_dmat *sQ,
+                                          const struct blasfeo_dmat *sE,
+                                          const struct blasfeo_dmat *sL,
+                                          const struct blasfeo_dmat *sX,
+                                          int *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLASFEO_HIP_H */

@@ -1,0 +1,321 @@
+"""Python binding of libblasfeo_hip.so, an MI355X (gfx950) library of panel-major
+dense linear algebra routines after BLASFEO (arXiv 1704.02457).
+
+This layer only marshals arguments: every computation runs in the HIP kernels
+of the shared library, reached through its C ABI (include/blasfeo_hip.h).
+PyTorch is used for device memory (``torch.empty(..., device="cuda")``) and
+streams.  If the library is not built, or no GPU is present, the compute
+functions raise; there is no CPU fallback.
+
+Function names are those of the C ABI.  A ``DMat`` carries a device buffer and
+the ``struct blasfeo_dmat`` describing it; a ``DMatBatch`` is a uniform batch
+(instance b starts ``memsize`` bytes after instance b-1) whose struct describes
+instance 0, as the batched entry points expect.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblasfeo_hip.so")
+PS = 16
+
+_lib = None
+
+
+class blasfeo_dmat(ctypes.Structure):
+    _fields_ = [("pA", ctypes.c_void_p), ("dA", ctypes.c_void_p), ("m", ctypes.c_int),
+                ("n", ctypes.c_int), ("pm", ctypes.c_int), ("cn", ctypes.c_int),
+                ("use_dA", ctypes.c_int), ("memsize", ctypes.c_int)]
+
+
+class blasfeo_dvec(ctypes.Structure):
+    _fields_ = [("pa", ctypes.c_void_p), ("m", ctypes.c_int), ("pm", ctypes.c_int),
+                ("memsize", ctypes.c_int)]
+
+
+_M = ctypes.POINTER(blasfeo_dmat)
+_V = ctypes.POINTER(blasfeo_dvec)
+_i, _d, _p, _ll = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "blasfeo_memsize_dmat": (_i, [_i, _i]),
+    "blasfeo_memsize_dvec": (_i, [_i]),
+    "blasfeo_create_dmat": (None, [_i, _i, _M, _p]),
+    "blasfeo_create_dvec": (None, [_i, _V, _p]),
+    "blasfeo_allocate_dmat": (None, [_i, _i, _M]),
+    "blasfeo_free_dmat": (None, [_M]),
+    "blasfeo_allocate_dvec": (None, [_i, _V]),
+    "blasfeo_free_dvec": (None, [_V]),
+    "blasfeo_pack_dmat": (None, [_i, _i, _p, _i, _M, _i, _i]),
+    "blasfeo_unpack_dmat": (None, [_i, _i, _M, _i, _i, _p, _i]),
+    "blasfeo_pack_dvec": (None, [_i, _p, _V, _i]),
+    "blasfeo_unpack_dvec": (None, [_i, _V, _i, _p]),
+    "blasfeo_dgemm_nt": (None, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dsyrk_ln": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dtrsm_rltn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dpotrf_l": (None, [_i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dsyrk_dpotrf_ln": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_hip_dpotrf_l_info": (None, [_i, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dsyrk_dpotrf_ln_info": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_set_stream": (None, [_p]),
+    "blasfeo_hip_get_stream": (_p, []),
+    "blasfeo_hip_get_last_error": (_i, []),
+    "blasfeo_hip_strerror": (ctypes.c_char_p, [_i]),
+    "blasfeo_hip_version": (_i, []),
+    "blasfeo_hip_pack_dmat_batched": (_i, [_i, _i, _i, _p, _i, _ll, _M, _i, _i, _p]),
+    "blasfeo_hip_unpack_dmat_batched": (_i, [_i, _i, _i, _M, _i, _i, _p, _i, _ll, _p]),
+    "blasfeo_hip_dgemm_nt_batched": (_i, [_i, _i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dsyrk_ln_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dtrsm_rltn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
+    "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
+}
+
+
+def lib():
+    """Load libblasfeo_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1704_02457_amd.build` "
+                               "or __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+class HipError(RuntimeError):
+    pass
+
+
+def check(code):
+    """Raise HipError for a nonzero return code of a batched entry point."""
+    if code != 0:
+        raise HipError(f"blasfeo_hip error {code}: {lib().blasfeo_hip_strerror(code).decode()}")
+    return code
+
+
+def check_last():
+    """Raise HipError if a single-instance routine recorded an error."""
+    check(lib().blasfeo_hip_get_last_error())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1704_02457_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def memsize_dmat(m, n):
+    return lib().blasfeo_memsize_dmat(m, n)
+
+
+class DMat:
+    """A device panel-major matrix: torch storage + struct blasfeo_dmat."""
+
+    def __init__(self, m, n, device="cuda", storage=None, offset_bytes=0):
+        torch = _torch()
+        self.s = blasfeo_dmat()
+        ms = lib().blasfeo_memsize_dmat(m, n)
+        if ms < 0:
+            raise ValueError("bad size")
+        if storage is None:
+            storage = torch.empty(max(ms, 256) // 8, dtype=torch.float64, device=device)
+        self.buf = storage
+        lib().blasfeo_create_dmat(m, n, ctypes.byref(self.s), ctypes.c_void_p(storage.data_ptr() + offset_bytes))
+        self.m, self.n = m, n
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    @property
+    def memsize(self):
+        return self.s.memsize
+
+    def panels(self):
+        """The panel storage as a flat float64 tensor view (pm*16*cn)."""
+        return self.buf[: self.s.pm * PS * self.s.cn]
+
+    def dA(self):
+        off = self.s.pm * PS * self.s.cn
+        return self.buf[off: off + max(self.m, self.n)]
+
+
+class DMatBatch:
+    """`batch` consecutive DMat chunks of memsize bytes; .s describes instance 0."""
+
+    def __init__(self, batch, m, n, device="cuda", fill=None):
+        torch = _torch()
+        self.batch, self.m, self.n = batch, m, n
+        ms = lib().blasfeo_memsize_dmat(m, n)
+        self.stride = ms // 8
+        if fill is None:
+            self.buf = torch.empty(max(batch * self.stride, 32), dtype=torch.float64, device=device)
+        else:
+            self.buf = torch.full((max(batch * self.stride, 32),), fill, dtype=torch.float64, device=device)
+        self.s = blasfeo_dmat()
+        lib().blasfeo_create_dmat(m, n, ctypes.byref(self.s), ctypes.c_void_p(self.buf.data_ptr()))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    def instances(self):
+        """(batch, memsize/8) view of the raw chunks."""
+        return self.buf[: self.batch * self.stride].view(self.batch, self.stride)
+
+    def dA(self):
+        off = self.s.pm * PS * self.s.cn
+        return self.instances()[:, off: off + max(self.m, self.n)]
+
+
+# ------------------------------------------------------------------ packing
+
+def pack(A, out=None, bi=0, bj=0):
+    """Column-major copy of the (m, n) tensor A (any layout, on the GPU) into a
+    DMat (panel-major) through blasfeo_pack_dmat."""
+    torch = _torch()
+    m, n = A.shape
+    At = A.t().contiguous().to(torch.float64)  # (n, m) row-major == column-major A
+    if out is None:
+        out = DMat(m, n, device=A.device)
+    lib().blasfeo_pack_dmat(m, n, ctypes.c_void_p(At.data_ptr()), max(m, 1), out.ref, bi, bj)
+    check_last()
+    return out
+
+
+def unpack(sA, m=None, n=None, ai=0, aj=0):
+    """(m, n) tensor of the sub-matrix of DMat sA at (ai, aj)."""
+    torch = _torch()
+    m = sA.m - ai if m is None else m
+    n = sA.n - aj if n is None else n
+    out = torch.empty((n, m), dtype=torch.float64, device=sA.buf.device)
+    lib().blasfeo_unpack_dmat(m, n, sA.ref, ai, aj, ctypes.c_void_p(out.data_ptr()), max(m, 1))
+    check_last()
+    return out.t()
+
+
+def pack_batch(A, out=None):
+    """(batch, m, n) tensor -> DMatBatch (panel-major) via the batched pack."""
+    torch = _torch()
+    batch, m, n = A.shape
+    At = A.transpose(1, 2).contiguous().to(torch.float64)  # per instance column-major
+    if out is None:
+        out = DMatBatch(batch, m, n, device=A.device)
+    check(lib().blasfeo_hip_pack_dmat_batched(batch, m, n, ctypes.c_void_p(At.data_ptr()), max(m, 1),
+                                              m * n, out.ref, 0, 0, _stream()))
+    return out
+
+
+def unpack_batch(sA, m=None, n=None):
+    torch = _torch()
+    m = sA.m if m is None else m
+    n = sA.n if n is None else n
+    out = torch.empty((sA.batch, n, m), dtype=torch.float64, device=sA.buf.device)
+    check(lib().blasfeo_hip_unpack_dmat_batched(sA.batch, m, n, sA.ref, 0, 0, ctypes.c_void_p(out.data_ptr()),
+                                                max(m, 1), m * n, _stream()))
+    return out.transpose(1, 2)
+
+
+# ------------------------------------------------------------------ routines (C ABI names)
+
+def _sync_stream():
+    lib().blasfeo_hip_set_stream(ctypes.c_void_p(_stream()))
+
+
+def blasfeo_dgemm_nt(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dgemm_nt(m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_dsyrk_ln(m, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dsyrk_ln(m, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_dtrsm_rltn(m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dtrsm_rltn(m, n, alpha, sA.ref, ai, aj, sB.ref, bi, bj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_dpotrf_l(m, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dpotrf_l(m, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_dsyrk_dpotrf_ln(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dsyrk_dpotrf_ln(m, k, sA.ref, ai, aj, sB.ref, bi, bj, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_hip_dpotrf_l_info(m, sC, ci, cj, sD, di, dj, info):
+    _sync_stream()
+    lib().blasfeo_hip_dpotrf_l_info(m, sC.ref, ci, cj, sD.ref, di, dj, _ptr(info))
+    check_last()
+
+
+def blasfeo_hip_dsyrk_dpotrf_ln_info(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, sD, di, dj, info):
+    _sync_stream()
+    lib().blasfeo_hip_dsyrk_dpotrf_ln_info(m, k, sA.ref, ai, aj, sB.ref, bi, bj, sC.ref, ci, cj, sD.ref, di, dj,
+                                           _ptr(info))
+    check_last()
+
+
+def blasfeo_hip_dgemm_nt_batched(batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
+                                 stream=None):
+    return check(lib().blasfeo_hip_dgemm_nt_batched(batch, m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
+                                                    sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_dsyrk_ln_batched(batch, m, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
+                                 stream=None):
+    return check(lib().blasfeo_hip_dsyrk_ln_batched(batch, m, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
+                                                    sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_dtrsm_rltn_batched(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj, stream=None):
+    return check(lib().blasfeo_hip_dtrsm_rltn_batched(batch, m, n, alpha, sA.ref, ai, aj, sB.ref, bi, bj,
+                                                      sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_dpotrf_l_batched(batch, m, sC, ci, cj, sD, di, dj, info, stream=None):
+    return check(lib().blasfeo_hip_dpotrf_l_batched(batch, m, sC.ref, ci, cj, sD.ref, di, dj, _ptr(info),
+                                                    _stream(stream)))
+
+
+def blasfeo_hip_dsyrk_dpotrf_trsm_batched(batch, m, k, nrhs, sA, sQ, sE, sL, sX, info, stream=None):
+    return check(lib().blasfeo_hip_dsyrk_dpotrf_trsm_batched(
+        batch, m, k, nrhs, sA.ref if sA is not None else None, sQ.ref, sE.ref if sE is not None else None,
+        sL.ref, sX.ref if sX is not None else None, _ptr(info), _stream(stream)))

@@ -1,0 +1,417 @@
+// Generic panel-major level-3 routines: gemm_nt, syrk_ln, trsm_rltn,
+// potrf_l and syrk_potrf_ln on arbitrary sub-matrices (any (ai, aj), any
+// sizes), single instance or uniform batch (one batch index per grid row).
+//
+// These are the "generic" kernel variant of §4.4.2: every 16x16 block is
+// computed as a full register tile and stored through a masked store that
+// also handles sub-matrices not aligned to a panel top.  Operands are read
+// straight from the caller's panel-major buffers; nothing is repacked (§4.3).
+#include "common.hpp"
+
+namespace bh {
+
+constexpr int GW = 4;  // waves per workgroup in the generic kernels
+
+__device__ __forceinline__ View at_batch(View v, long long stride) {
+  v.p += (long long)blockIdx.y * stride;
+  return v;
+}
+
+// ---------------------------------------------------------------- gemm/syrk
+// One wave per 16x16 block of D.  The wave accumulates the transposed block
+// D^T(j,i) = sum_k B_j[:,k] A_i[:,k]^T with one MFMA per 4-wide k-step (the
+// gemm_nt k-loop of §4.4.1: both factors are read along panels), then
+// applies alpha/beta and stores with the generic masked store.
+template <bool SYRK>
+__global__ __launch_bounds__(64 * GW) void k_gemm_nt(
+    int m, int n, int k, double alpha, View A, View B, double beta, View C,
+    View D, long long sA, long long sB, long long sC, long long sD) {
+  A = at_batch(A, sA);
+  B = at_batch(B, sB);
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const int w = threadIdx.x >> 6;
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+  const int tile = blockIdx.x * GW + w;
+  int ti, tj;
+  if (SYRK) {
+    // lower block triangle, row-major enumeration: tile = ti*(ti+1)/2 + tj
+    if (tile >= tm * (tm + 1) / 2) return;
+    ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+    tj = tile - ti * (ti + 1) / 2;
+  } else {
+    if (tile >= tm * tn) return;
+    ti = tile / tn;
+    tj = tile - ti * tn;
+  }
+  d4 acc = zero4();
+  for (int k0 = 0; k0 < k; k0 += 4) {
+    const double fb = load_frag(B, 16 * tj, k0);
+    const double fa = load_frag(A, 16 * ti, k0);
+    acc = mfma(fb, fa, acc);
+  }
+  const d4 ct = load_tileT(C, 16 * ti, 16 * tj, SYRK);
+  d4 out;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = beta * ct[r] + alpha * acc[r];
+  store_tileT(D, 16 * ti, 16 * tj, out, SYRK);
+}
+
+// ---------------------------------------------------------------- trsm_rltn
+// D = alpha * B * A^{-T}, A lower.  In the transposed view Y = D^T solves
+// A*Y = alpha*B^T by block forward substitution; each wave owns 16 rows of B
+// (16 columns of Y) and walks the block rows of A.  For block row j:
+//   Z = alpha*B^T(j) - sum_{l<j} A(j,l) Y(l)          (MFMA downdate)
+//   Y(j) = A(j,j)^{-1} Z                               (MFMA with the
+//          register-computed inverse of the diagonal block)
+// The gemm downdate and the substitution run in one kernel (§4.6, "trsm as
+// one kernel").  Earlier Y(l) are re-read from D, which this wave wrote.
+__device__ __forceinline__ void diag_inverse_lower(const View &A, int j0,
+                                                   int nv, WaveLds &s,
+                                                   d4 &V) {
+  // W^T (upper) of the lower diagonal block W = A(j0:j0+16, j0:j0+16)
+  d4 Wt = load_tileT(A, j0, j0, true);
+  pad_identity(Wt, nv);
+  const int l = lane_id();
+  if (l < 16) {
+    const double d = (l < nv) ? A.p[pm_off(A.ai + j0 + l, A.aj + j0 + l, A.cn)]
+                              : 1.0;
+    s.inv[l] = 1.0 / d;
+  }
+  wave_sync();
+  V = trtri_tile_upper(Wt, s.inv, s.ulds, s.row);
+}
+
+__global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
+    int m, int n, double alpha, View A, View B, View D, long long sA,
+    long long sB, long long sD) {
+  A = at_batch(A, sA);
+  B = at_batch(B, sB);
+  D = at_batch(D, sD);
+  __shared__ WaveLds lds[GW];
+  const int w = threadIdx.x >> 6;
+  const int strip = blockIdx.x * GW + w;  // 16 rows of B
+  if (strip * 16 >= m) return;
+  WaveLds &s = lds[w];
+  const int nb = (n + 15) >> 4;
+  for (int j = 0; j < nb; ++j) {
+    d4 z = load_tileT(B, 16 * strip, 16 * j, false);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[r] *= alpha;
+    for (int l = 0; l < j; ++l) {
+      const d4 a = load_tileT(A, 16 * j, 16 * l, false);  // A(j,l)^T
+      const d4 y = load_tileT(D, 16 * strip, 16 * l, false);  // Y(l)
+      z = mfma_tn(neg4(a), y, z);
+    }
+    d4 V;
+    diag_inverse_lower(A, 16 * j, min(16, n - 16 * j), s, V);
+    const d4 y = mfma_tn(V, z, zero4());
+    store_tileT(D, 16 * strip, 16 * j, y, false);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- potrf_l
+// Lower Cholesky of C (+ A*B^T when k > 0), one workgroup per instance.
+// Left-looking over block columns j of L, i.e. block rows j of U = L^T: every
+// 16x16 block is produced once by one kernel pass -- the gemm_nt downdate
+// over the already computed blocks, then either the register-resident
+// factorization (diagonal block) or the triangular solve with the diagonal
+// block's inverse (off-diagonal blocks) -- and stored (§4.6: LAPACK routines
+// written as BLAS-like kernels, block size = kernel size).
+struct PotrfLds {
+  WaveLds w;
+  double V[64 * 4];  // inverse of the current diagonal block (T-tile)
+  int info;
+};
+
+__global__ __launch_bounds__(64 * GW) void k_potrf_l(
+    int m, int k, View A, View B, View C, View D, double *dA, int *info,
+    long long sA, long long sB, long long sC, long long sD, long long sdA) {
+  A = at_batch(A, sA);
+  B = at_batch(B, sB);
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *dAb = dA ? dA + b * sdA : nullptr;
+  __shared__ PotrfLds s;
+  const int w = threadIdx.x >> 6;
+  const int l = lane_id();
+  const int nb = (m + 15) >> 4;
+  if (threadIdx.x == 0) s.info = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const int nv = min(16, m - 16 * j);
+    if (w == 0) {
+      d4 t = load_tileT(C, 16 * j, 16 * j, true);
+      for (int k0 = 0; k0 < k; k0 += 4)
+        t = mfma(load_frag(B, 16 * j, k0), load_frag(A, 16 * j, k0), t);
+      for (int q = 0; q < j; ++q) {
+        const d4 u = load_tileT(D, 16 * j, 16 * q, false);  // U(q,j)
+        t = mfma_tn(neg4(u), u, t);
+      }
+      pad_identity(t, nv);
+      const int inf = potrf_tile_upper(t, s.w.row, s.w.inv);
+      if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
+      store_tileT(D, 16 * j, 16 * j, t, true);
+      if (dAb && l < nv) dAb[16 * j + l] = s.w.inv[l];
+      const d4 v = trtri_tile_upper(t, s.w.inv, s.w.ulds, s.w.row);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.V[l * 4 + r] = v[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    d4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = s.V[l * 4 + r];
+    for (int i = j + 1 + w; i < nb; i += GW) {
+      d4 t = load_tileT(C, 16 * i, 16 * j, false);  // M(j,i) = C(i,j)^T
+      for (int k0 = 0; k0 < k; k0 += 4)
+        t = mfma(load_frag(B, 16 * j, k0), load_frag(A, 16 * i, k0), t);
+      for (int q = 0; q < j; ++q) {
+        const d4 uj = load_tileT(D, 16 * j, 16 * q, false);  // U(q,j)
+        const d4 ui = load_tileT(D, 16 * i, 16 * q, false);  // U(q,i)
+        t = mfma_tn(neg4(uj), ui, t);
+      }
+      const d4 u = mfma_tn(v, t, zero4());  // U(j,i) = V^T M(j,i)
+      store_tileT(D, 16 * i, 16 * j, u, false);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  }
+  if (info && threadIdx.x == 0) info[b] = s.info;
+}
+
+// ---------------------------------------------------------------- launchers
+
+int launch_gemm(bool syrk, int batch, int m, int n, int k, double alpha,
+                const blasfeo_dmat *sA, int ai, int aj, const blasfeo_dmat *sB,
+                int bi, int bj, double beta, const blasfeo_dmat *sC, int ci,
+                int cj, const blasfeo_dmat *sD, int di, int dj,
+                hipStream_t st) {
+  if (batch == 0 || m == 0 || n == 0) return 0;
+  const int tm = (m + 15) / 16, tn = (n + 15) / 16;
+  const int tiles = syrk ? tm * (tm + 1) / 2 : tm * tn;
+  dim3 grid((tiles + GW - 1) / GW, batch);
+  View A = make_view(sA, ai, aj, m, k);
+  View B = make_view(sB, bi, bj, n, k);
+  View C = make_view(sC, ci, cj, m, n);
+  View D = make_view(sD, di, dj, m, n);
+  if (syrk)
+    hipLaunchKernelGGL(k_gemm_nt<true>, grid, dim3(64 * GW), 0, st, m, n, k,
+                       alpha, A, B, beta, C, D, batch_stride(sA),
+                       batch_stride(sB), batch_stride(sC), batch_stride(sD));
+  else
+    hipLaunchKernelGGL(k_gemm_nt<false>, grid, dim3(64 * GW), 0, st, m, n,
+                       k, alpha, A, B, beta, C, D, batch_stride(sA),
+                       batch_stride(sB), batch_stride(sC), batch_stride(sD));
+  return launch_status();
+}
+
+int launch_trsm(int batch, int m, int n, double alpha, const blasfeo_dmat *sA,
+                int ai, int aj, const blasfeo_dmat *sB, int bi, int bj,
+                const blasfeo_dmat *sD, int di, int dj, hipStream_t st) {
+  if (batch == 0 || m == 0 || n == 0) return 0;
+  const int strips = (m + 15) / 16;
+  dim3 grid((strips + GW - 1) / GW, batch);
+  View A = make_view(sA, ai, aj, n, n);
+  View B = make_view(sB, bi, bj, m, n);
+  View D = make_view(sD, di, dj, m, n);
+  hipLaunchKernelGGL(k_trsm_rltn, grid, dim3(64 * GW), 0, st, m, n, alpha,
+                     A, B, D, batch_stride(sA), batch_stride(sB),
+                     batch_stride(sD));
+  return launch_status();
+}
+
+int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
+                 int aj, const blasfeo_dmat *sB, int bi, int bj,
+                 const blasfeo_dmat *sC, int ci, int cj,
+                 const blasfeo_dmat *sD, int di, int dj, int *info,
+                 hipStream_t st) {
+  if (batch == 0) return 0;
+  if (m == 0) {
+    if (info) {
+      hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * batch, st);
+      return e == hipSuccess ? 0 : (int)e;
+    }
+    return 0;
+  }
+  View A{}, B{};
+  if (k > 0) {
+    A = make_view(sA, ai, aj, m, k);
+    B = make_view(sB, bi, bj, m, k);
+  }
+  View C = make_view(sC, ci, cj, m, m);
+  View D = make_view(sD, di, dj, m, m);
+  hipLaunchKernelGGL(k_potrf_l, dim3(1, batch), dim3(64 * GW), 0, st, m, k,
+                     A, B, C, D, sD->dA, info,
+                     k > 0 ? batch_stride(sA) : 0, k > 0 ? batch_stride(sB) : 0,
+                     batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  return launch_status();
+}
+
+}  // namespace bh
+
+using namespace bh;
+
+extern "C" {
+
+void blasfeo_dgemm_nt(int m, int n, int k, double alpha,
+                      struct blasfeo_dmat *sA, int ai, int aj,
+                      struct blasfeo_dmat *sB, int bi, int bj, double beta,
+                      struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (n < 0) return set_error(-2);
+  if (k < 0) return set_error(-3);
+  if (!operand_ok(sA, ai, aj, m, k)) return set_error(-5);
+  if (!operand_ok(sB, bi, bj, n, k)) return set_error(-8);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-12);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-15);
+  set_error(launch_gemm(false, 1, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
+                        beta, sC, ci, cj, sD, di, dj, tl_stream()));
+}
+
+void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
+                      int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                      int bj, double beta, struct blasfeo_dmat *sC, int ci,
+                      int cj, struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (k < 0) return set_error(-2);
+  if (!operand_ok(sA, ai, aj, m, k)) return set_error(-4);
+  if (!operand_ok(sB, bi, bj, m, k)) return set_error(-7);
+  if (!operand_ok(sC, ci, cj, m, m)) return set_error(-11);
+  if (!operand_ok(sD, di, dj, m, m)) return set_error(-14);
+  set_error(launch_gemm(true, 1, m, m, k, alpha, sA, ai, aj, sB, bi, bj,
+                        beta, sC, ci, cj, sD, di, dj, tl_stream()));
+}
+
+void blasfeo_dtrsm_rltn(int m, int n, double alpha, struct blasfeo_dmat *sA,
+                        int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                        int bj, struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (n < 0) return set_error(-2);
+  if (!operand_ok(sA, ai, aj, n, n)) return set_error(-4);
+  if (!operand_ok(sB, bi, bj, m, n)) return set_error(-7);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-10);
+  set_error(launch_trsm(1, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
+                        tl_stream()));
+}
+
+void blasfeo_hip_dpotrf_l_info(int m, struct blasfeo_dmat *sC, int ci,
+                               int cj, struct blasfeo_dmat *sD, int di,
+                               int dj, int *info) {
+  if (m < 0) return set_error(-1);
+  if (!operand_ok(sC, ci, cj, m, m)) return set_error(-2);
+  if (!operand_ok(sD, di, dj, m, m)) return set_error(-5);
+  if (m > 0 && !sD->dA) return set_error(-5);
+  int e = launch_potrf(1, m, 0, nullptr, 0, 0, nullptr, 0, 0, sC, ci, cj, sD,
+                       di, dj, info, tl_stream());
+  if (e == 0) sD->use_dA = (di == 0 && dj == 0);
+  set_error(e);
+}
+
+void blasfeo_dpotrf_l(int m, struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj) {
+  blasfeo_hip_dpotrf_l_info(m, sC, ci, cj, sD, di, dj, nullptr);
+}
+
+void blasfeo_hip_dsyrk_dpotrf_ln_info(int m, int k, struct blasfeo_dmat *sA,
+                                      int ai, int aj,
+                                      struct blasfeo_dmat *sB, int bi,
+                                      int bj, struct blasfeo_dmat *sC,
+                                      int ci, int cj,
+                                      struct blasfeo_dmat *sD, int di,
+                                      int dj, int *info) {
+  if (m < 0) return set_error(-1);
+  if (k < 0) return set_error(-2);
+  if (!operand_ok(sA, ai, aj, m, k)) return set_error(-3);
+  if (!operand_ok(sB, bi, bj, m, k)) return set_error(-6);
+  if (!operand_ok(sC, ci, cj, m, m)) return set_error(-9);
+  if (!operand_ok(sD, di, dj, m, m)) return set_error(-12);
+  if (m > 0 && !sD->dA) return set_error(-12);
+  int e = launch_potrf(1, m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, sD, di,
+                       dj, info, tl_stream());
+  if (e == 0) sD->use_dA = (di == 0 && dj == 0);
+  set_error(e);
+}
+
+void blasfeo_dsyrk_dpotrf_ln(int m, int k, struct blasfeo_dmat *sA, int ai,
+                             int aj, struct blasfeo_dmat *sB, int bi,
+                             int bj, struct blasfeo_dmat *sC, int ci,
+                             int cj, struct blasfeo_dmat *sD, int di,
+                             int dj) {
+  blasfeo_hip_dsyrk_dpotrf_ln_info(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj,
+                                   sD, di, dj, nullptr);
+}
+
+int blasfeo_hip_dgemm_nt_batched(int batch, int m, int n, int k,
+                                 double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (k < 0) return -4;
+  if (!operand_ok(sA, ai, aj, m, k)) return -6;
+  if (!operand_ok(sB, bi, bj, n, k)) return -9;
+  if (!operand_ok(sC, ci, cj, m, n)) return -13;
+  if (!operand_ok(sD, di, dj, m, n)) return -16;
+  return launch_gemm(false, batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
+                     beta, sC, ci, cj, sD, di, dj, (hipStream_t)stream);
+}
+
+int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (k < 0) return -3;
+  if (!operand_ok(sA, ai, aj, m, k)) return -5;
+  if (!operand_ok(sB, bi, bj, m, k)) return -8;
+  if (!operand_ok(sC, ci, cj, m, m)) return -12;
+  if (!operand_ok(sD, di, dj, m, m)) return -15;
+  return launch_gemm(true, batch, m, m, k, alpha, sA, ai, aj, sB, bi, bj,
+                     beta, sC, ci, cj, sD, di, dj, (hipStream_t)stream);
+}
+
+int blasfeo_hip_dtrsm_rltn_batched(int batch, int m, int n, double alpha,
+                                   const struct blasfeo_dmat *sA, int ai,
+                                   int aj, const struct blasfeo_dmat *sB,
+                                   int bi, int bj,
+                                   const struct blasfeo_dmat *sD, int di,
+                                   int dj, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!operand_ok(sA, ai, aj, n, n)) return -5;
+  if (!operand_ok(sB, bi, bj, m, n)) return -8;
+  if (!operand_ok(sD, di, dj, m, n)) return -11;
+  return launch_trsm(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
+                     (hipStream_t)stream);
+}
+
+int blasfeo_hip_dpotrf_l_batched(int batch, int m,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, int *info, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (!operand_ok(sC, ci, cj, m, m)) return -3;
+  if (!operand_ok(sD, di, dj, m, m)) return -6;
+  if (m > 0 && !sD->dA) return -6;
+  return launch_potrf(batch, m, 0, nullptr, 0, 0, nullptr, 0, 0, sC, ci, cj,
+                      sD, di, dj, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,339 @@
+// Device building blocks shared by all kernels: the counterpart of the
+// paper's assembly subroutines (§4.4.1) -- fragment loads from panel-major
+// storage, the MFMA k-loop, the register-resident 16x16 factorization and
+// inversion, masked/unaligned stores -- written as forceinline device
+// functions that pass 16x16 tiles in registers.
+//
+// Register tile ("T-tile") convention.  A 16x16 FP64 tile lives in the
+// result layout of v_mfma_f64_16x16x4f64 on gfx950: lane l = c + 16*g
+// (c = l & 15, g = l >> 4) holds in register r the element in row g + 4r,
+// column c.  Two facts make this layout the work-horse of the library:
+//   * register r of a T-tile X is exactly the B operand of the k-step
+//     covering rows 4r..4r+3 of X, and the A operand of the same k-step of
+//     X^T, so  sum_r mfma(X[r], Y[r])  =  X^T * Y  for T-tiles X, Y;
+//   * loading the TRANSPOSE of a 16x16 block of a panel-major matrix into a
+//     T-tile reads, for register r, the 64 consecutive doubles
+//     [64r, 64r+64) of the block's 16 panel columns: one contiguous 512-byte
+//     wave transaction (§4.3's "data is read along panels").
+// The kernels therefore work on transposed blocks: a lower factor L is held
+// as its transpose U = L^T, and every trailing update, triangular solve and
+// product is a chain of MFMAs on register tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bh {
+
+constexpr int PS = 16;  // panel height (rows per panel), double precision
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Offset of element (i, j) in a panel-major buffer with panel length cn
+// (§4.3): (i - i % ps) * cn + j * ps + i % ps.
+__host__ __device__ __forceinline__ long long pm_off(int i, int j, int cn) {
+  return (long long)(i & ~(PS - 1)) * cn + (long long)j * PS + (i & (PS - 1));
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Orders LDS traffic of one wavefront (no hardware barrier needed: a wave's
+// LDS instructions execute in issue order; this stops compiler reordering).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ d4 zero4() { return (d4){0.0, 0.0, 0.0, 0.0}; }
+
+// acc += X^T * Y for T-tiles X, Y (four chained MFMAs).
+__device__ __forceinline__ d4 mfma_tn(const d4 &X, const d4 &Y, d4 acc) {
+  acc = mfma(X[0], Y[0], acc);
+  acc = mfma(X[1], Y[1], acc);
+  acc = mfma(X[2], Y[2], acc);
+  acc = mfma(X[3], Y[3], acc);
+  return acc;
+}
+
+__device__ __forceinline__ d4 neg4(const d4 &x) { return -x; }
+
+// ---------------------------------------------------------------------------
+// Buffer-resource accesses: a 128-bit descriptor (base, size in bytes) in
+// SGPRs plus a 32-bit per-lane byte offset and a uniform byte offset.  The
+// kernels address every operand of an instance through one descriptor, so
+// an access costs one VGPR offset instead of a 64-bit address.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t brsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// dword 3 of a raw (untyped, stride 0) buffer descriptor on gfx9-family GPUs
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ brsrc make_rsrc(const void *base, long long bytes) {
+  const int n = bytes > 0x7fffffffLL ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, n,
+                                           kBufferWord3);
+}
+
+__device__ __forceinline__ double bload(brsrc r, int voff, int soff) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(brsrc r, int voff, int soff, double x) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Generic (any offset, any bounds) accesses.  A "view" is a panel-major
+// matrix with its sub-matrix origin (ai, aj) and the sub-matrix extent.
+// ---------------------------------------------------------------------------
+struct View {
+  double *p;
+  int cn;
+  int ai, aj;
+  int rows, cols;  // extent of the sub-matrix
+};
+
+// A/B operand fragment of the 16x4 block X = S[i0:i0+16, k0:k0+4] of the
+// sub-matrix S: lane l holds X[l & 15][l >> 4] (zero outside S).  Used as
+// the A operand it supplies X; used as the B operand it supplies X^T.
+__device__ __forceinline__ double load_frag(const View &v, int i0, int k0) {
+  const int l = lane_id();
+  const int i = i0 + (l & 15), k = k0 + (l >> 4);
+  double x = 0.0;
+  if (i < v.rows && k < v.cols) x = v.p[pm_off(v.ai + i, v.aj + k, v.cn)];
+  return x;
+}
+
+// T-tile holding the transpose of the block S[i0:i0+16, j0:j0+16]:
+// register r of lane (c, g) = S[i0 + c][j0 + g + 4r].  Elements outside S,
+// and, if lower_only, elements above the diagonal of S (i < j), read as 0.
+__device__ __forceinline__ d4 load_tileT(const View &v, int i0, int j0,
+                                         bool lower_only) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + c, j = j0 + g + 4 * r;
+    double x = 0.0;
+    if (i < v.rows && j < v.cols && (!lower_only || i >= j))
+      x = v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
+    t[r] = x;
+  }
+  return t;
+}
+
+// Stores the T-tile t (holding the transpose of a block) into
+// S[i0:i0+16, j0:j0+16], masked to S and, if lower_only, to i >= j.
+__device__ __forceinline__ void store_tileT(const View &v, int i0, int j0,
+                                            const d4 &t, bool lower_only) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + c, j = j0 + g + 4 * r;
+    if (i < v.rows && j < v.cols && (!lower_only || i >= j))
+      v.p[pm_off(v.ai + i, v.aj + j, v.cn)] = t[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident 16x16 Cholesky and triangular inversion (§4.6: the
+// "unblocked" LAPACK part is a subroutine on a register-resident block).
+// ---------------------------------------------------------------------------
+
+// Upper Cholesky factorization of a T-tile.  On entry T holds a symmetric
+// block in its upper triangle (rows <= cols); the strictly lower part is
+// ignored.  Rows/cols >= nv are padding and must hold the identity on entry
+// (they stay the identity).  On exit T = U (upper, zero below the diagonal)
+// with U^T U = block, and inv[k] = 1/U[k][k] (LDS, 16 doubles).  Column k is
+// formed from the definition: U[k][k] = sqrt(d_k), U[k][c] = T[k][c]*(1/U[k][k])
+// followed by the rank-1 downdate of the trailing block, for k ascending.
+// `row` is 16 doubles of wave-private LDS.  Returns 0 or k+1 for the first
+// pivot d_k that is not > 0; such a pivot gets inv[k] = 0, which keeps every
+// entry of the earlier rows (columns of L) finite and exact; later entries
+// are unspecified.
+__device__ __forceinline__ int potrf_tile_upper(d4 &T, double *row,
+                                                double *inv) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  int info = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int rk = k >> 2, gk = k & 3;
+    if (g == gk) row[c] = T[rk];
+    wave_sync();
+    const double d = row[k];
+    const double ukk = sqrt(d);
+    // a failed pivot gets a zero reciprocal: its row of U is zeroed instead
+    // of filled with NaN, so the columns before it stay exact
+    const bool ok = d > 0.0;
+    const double iv = ok ? 1.0 / ukk : 0.0;
+    if (!ok && info == 0) info = k + 1;
+    const double ukc = (c > k) ? row[c] * iv : (c == k ? ukk : 0.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = g + 4 * r;
+      if (p > k && c > k) T[r] = T[r] - (row[p] * iv) * ukc;
+    }
+    if (g == gk) T[rk] = ukc;
+    if (l == 0) inv[k] = iv;
+    wave_sync();
+  }
+  // zero the strictly lower part
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (g + 4 * r > c) T[r] = 0.0;
+  return info;
+}
+
+// V = U^{-1} for an upper triangular T-tile U with inv[k] = 1/U[k][k]
+// (back substitution, one column per lane group column).  `ulds` is 256
+// doubles of wave-private LDS (U is staged there row-major), `row` is 16.
+// The strictly lower part of V is exactly zero.
+__device__ __forceinline__ d4 trtri_tile_upper(const d4 &U, const double *inv,
+                                               double *ulds, double *row) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ulds[(g + 4 * r) * 16 + c] = U[r];
+  wave_sync();
+  d4 s = zero4();
+  d4 V = zero4();
+#pragma unroll
+  for (int p = 15; p >= 0; --p) {
+    const int rp = p >> 2, gp = p & 3;
+    if (g == gp) {
+      const double v = ((p == c) ? 1.0 : 0.0) - s[rp];
+      V[rp] = v * inv[p];
+      row[c] = V[rp];
+    }
+    wave_sync();
+    const double vpc = row[c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = g + 4 * r;
+      if (q < p) s[r] = s[r] + ulds[q * 16 + p] * vpc;
+    }
+    wave_sync();
+  }
+  return V;
+}
+
+// Wave-private LDS scratch of the diagonal-block subroutines.
+struct WaveLds {
+  double ulds[256];
+  double row[16];
+  double inv[16];
+};
+
+// Scratch of potrf_inv_tile_upper: the two broadcast rows and a padded
+// 16x17 transpose buffer.
+struct DiagLds {
+  double rowU[16];
+  double rowW[16];
+  double inv[16];
+  double tr[16 * 17];
+};
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Upper Cholesky factorization of a T-tile together with the inverse of the
+// factor, in one sweep over the 16 pivots.
+//   In:  T holds a symmetric block in its upper triangle (rows <= cols);
+//        padding rows/cols >= nv must hold the identity.
+//   Out: T = U (upper, exact zeros below), V = U^{-1} (upper, T-tile),
+//        s.inv[k] = 1/U[k][k].  Returns 0 or k+1 for the first pivot that is
+//        not > 0; that pivot's reciprocal is set to 0 (see potrf_tile_upper).
+// Pivot k is U[k][k] = sqrt(d_k), U[k][c] = T[k][c]*(1/U[k][k]); at the same
+// time row k of W = L^{-1} = U^{-T} follows from forward substitution,
+//   W[k][c] = (delta_kc - S[k][c]) / U[k][k],  S[p][c] = sum_{q<p} U[q][p] W[q][c].
+// The 16 pivots are processed in four panels of four rows (one register of
+// the T-tile each).  Inside a panel the rank-1 downdates of T and updates of
+// S touch only the panel's rows; the panel's contribution to the rows below
+// is then one rank-4 MFMA for T and one for S (register b of a T-tile is the
+// MFMA operand of rows 4b..4b+3).  The pivot is fetched with readlane; the
+// pivot row of U and of W go through LDS once per pivot.  V is W^T (one LDS
+// transpose at the end).
+__device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
+                                                    DiagLds &s) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  int info = 0;
+  d4 S = zero4(), W = zero4();
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * b + kk;
+      const double d = readlane_d(T[b], k + 16 * kk);
+      const double ukk = sqrt(d);
+      const bool ok = d > 0.0;
+      const double iv = ok ? 1.0 / ukk : 0.0;
+      if (!ok && info == 0) info = k + 1;
+      // row k of U and of W, valid in lane group kk
+      const double ukc = (c > k) ? T[b] * iv : (c == k ? ukk : 0.0);
+      const double wkc = (((c == k) ? 1.0 : 0.0) - S[b]) * iv;
+      const bool mine = g == kk;
+      if (mine) {
+        s.rowU[c] = ukc;
+        s.rowW[c] = wkc;
+      }
+      T[b] = mine ? ukc : T[b];
+      W[b] = mine ? wkc : W[b];
+      if (l == 0) s.inv[k] = iv;
+      wave_sync();
+      // rank-1 downdate of the panel rows below the pivot (groups g > kk)
+      const double rc = s.rowU[c];
+      const double rp = s.rowU[4 * b + g];
+      const double rw = s.rowW[c];
+      const bool below = g > kk;
+      T[b] = (below && c > k) ? T[b] - rp * rc : T[b];
+      S[b] = below ? S[b] + rp * rw : S[b];
+      wave_sync();
+    }
+    if (b < 3) {
+      const double ub = T[b], wb = W[b];
+      const d4 Tn = mfma(-ub, ub, T);
+      const d4 Sn = mfma(ub, wb, S);
+#pragma unroll
+      for (int r = b + 1; r < 4; ++r) {
+        T[r] = Tn[r];
+        S[r] = Sn[r];
+      }
+    }
+  }
+  // V = W^T through a padded LDS transpose
+#pragma unroll
+  for (int r = 0; r < 4; ++r) s.tr[(g + 4 * r) * 17 + c] = W[r];
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) V[r] = s.tr[c * 17 + g + 4 * r];
+  wave_sync();
+  return info;
+}
+
+// Sets padding rows/columns (index >= nv) of a diagonal T-tile to the
+// identity so that the factorization of the padded block is blockdiag(U, I).
+__device__ __forceinline__ void pad_identity(d4 &T, int nv) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int p = g + 4 * r;
+    if (p >= nv || c >= nv) T[r] = (p == c) ? 1.0 : 0.0;
+  }
+}
+
+}  // namespace bh

@@ -1,0 +1,101 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, and its host-only logic (memsize, create, argument checks)
+behaves as documented.  No kernel is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1704_02457_amd as p
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "blasfeo_hip.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(blasfeo_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = p.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 30
+    for name in declared:
+        assert hasattr(L, name), name
+    # and the binding declares a signature for each of them
+    assert set(declared) <= set(p.exported_symbols())
+
+
+def _mk(m, n, addr=0x100000):
+    s = p.blasfeo_dmat()
+    p.lib().blasfeo_create_dmat(m, n, ctypes.byref(s), ctypes.c_void_p(addr))
+    return s
+
+
+@pytest.mark.parametrize("m,n", [(0, 0), (1, 1), (16, 16), (17, 3), (64, 64), (40, 40), (300, 7)])
+def test_memsize_and_create(m, n):
+    L = p.lib()
+    ms = L.blasfeo_memsize_dmat(m, n)
+    cn = (n + 3) // 4 * 4
+    pm = (m + 15) // 16
+    expect = pm * 16 * cn * 8 + max(m, n) * 8
+    expect = (expect + 255) // 256 * 256
+    assert ms == expect and ms % 256 == 0
+    s = _mk(m, n, 0x200000)
+    assert (s.m, s.n, s.cn, s.pm, s.memsize, s.use_dA) == (m, n, cn, pm, ms, 0)
+    assert s.pA == 0x200000
+    if pm * cn:
+        assert s.dA == 0x200000 + pm * 16 * cn * 8
+
+
+def test_memsize_errors_and_dvec():
+    L = p.lib()
+    assert L.blasfeo_memsize_dmat(-1, 3) == -1
+    assert L.blasfeo_memsize_dvec(-2) == -1
+    assert L.blasfeo_memsize_dvec(17) == 256
+    assert L.blasfeo_memsize_dvec(33) == 512
+
+
+def test_create_does_not_touch_memory():
+    # a pointer that is not mapped anywhere: create must only record it
+    s = _mk(32, 32, addr=0x10)
+    assert s.pA == 0x10
+
+
+def test_batched_argument_errors_before_launch():
+    L = p.lib()
+    A = _mk(64, 64)
+    X = _mk(16, 64)
+    small = _mk(8, 8)
+    r = lambda s: ctypes.byref(s)
+    f = L.blasfeo_hip_dsyrk_dpotrf_trsm_batched
+    assert f(-1, 64, 64, 16, r(A), r(A), r(X), r(A), r(X), None, None) == -1
+    assert f(1, 65, 64, 16, r(A), r(A), r(X), r(A), r(X), None, None) == -2
+    assert f(1, 64, -1, 16, r(A), r(A), r(X), r(A), r(X), None, None) == -3
+    assert f(1, 64, 64, 17, r(A), r(A), r(X), r(A), r(X), None, None) == -4
+    assert f(1, 64, 64, 16, r(small), r(A), r(X), r(A), r(X), None, None) == -5
+    assert f(1, 64, 64, 16, r(A), r(small), r(X), r(A), r(X), None, None) == -6
+    assert f(1, 64, 64, 16, r(A), r(A), r(small), r(A), r(X), None, None) == -7
+    assert f(1, 64, 64, 16, r(A), r(A), r(X), r(small), r(X), None, None) == -8
+    g = L.blasfeo_hip_dgemm_nt_batched
+    # B operand (n x k) out of bounds of its matrix
+    assert g(1, 64, 64, 64, 1.0, r(A), 0, 0, r(A), 1, 0, 1.0, r(A), 0, 0, r(A), 0, 0, None) == -9
+    assert g(1, 64, 64, 64, 1.0, r(A), 0, 0, r(A), 0, 0, 1.0, r(A), 0, 0, r(small), 0, 0, None) == -16
+    assert L.blasfeo_hip_dpotrf_l_batched(1, 9, r(small), 0, 0, r(small), 0, 0, None, None) == -3
+
+
+def test_single_routine_errors_recorded():
+    L = p.lib()
+    A = _mk(16, 16)
+    L.blasfeo_hip_get_last_error()
+    L.blasfeo_dgemm_nt(16, 16, 17, 1.0, ctypes.byref(A), 0, 0, ctypes.byref(A), 0, 0, 1.0,
+                       ctypes.byref(A), 0, 0, ctypes.byref(A), 0, 0)
+    assert L.blasfeo_hip_get_last_error() == -5
+    assert L.blasfeo_hip_get_last_error() == 0
+    L.blasfeo_dpotrf_l(-1, ctypes.byref(A), 0, 0, ctypes.byref(A), 0, 0)
+    assert L.blasfeo_hip_get_last_error() == -1
+    assert L.blasfeo_hip_strerror(-5) == b"invalid argument 5"

@@ -1,0 +1,290 @@
+"""GPU parity of the single-instance and uniform-batch routines against the
+CPU oracle, element by element, through the C ABI.  Operands live in
+panel-major device buffers filled by the library's pack routine; the pack and
+unpack kernels are themselves checked bit for bit against the independent
+numpy decoder of the panel layout."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import assert_parity, note
+from oracle import panel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1704_02457_amd as p  # noqa: E402
+
+DEV = torch.device("cuda:0")
+SENT = 7.25  # sentinel for elements that must not be written
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def mat(A):
+    """Pack a host (m, n) array into a new DMat."""
+    return p.pack(dev(A))
+
+
+def host(sA):
+    torch.cuda.synchronize()
+    return p.unpack(sA).cpu().numpy()
+
+
+def sentinel_mat(m, n):
+    return mat(np.full((m, n), SENT))
+
+
+# ------------------------------------------------------------------ pack / unpack
+
+@pytest.mark.parametrize("m,n", [(1, 1), (16, 16), (17, 5), (64, 64), (130, 37)])
+def test_pack_matches_independent_decoder(m, n):
+    note("pack", m, n)
+    rng = np.random.default_rng(m * 100 + n)
+    A = rng.standard_normal((m, n))
+    s = mat(A)
+    torch.cuda.synchronize()
+    raw = s.panels().cpu().numpy()
+    ref = panel.unpack(raw, m, n, s.s.cn, 16)
+    assert np.array_equal(ref, A)
+    assert np.array_equal(host(s), A)
+    # sub-matrix pack at an offset not aligned to a panel
+    big = sentinel_mat(m + 21, n + 3)
+    p.pack(dev(A), out=big, bi=21, bj=3)
+    full = host(big)
+    assert np.array_equal(full[21:, 3:], A)
+    mask = np.ones_like(full, dtype=bool)
+    mask[21:, 3:] = False
+    assert np.all(full[mask] == SENT)
+
+
+# ------------------------------------------------------------------ gemm_nt
+
+GEMM_CASES = [(64, 64, 64), (1, 1, 1), (17, 33, 5), (63, 65, 31), (100, 40, 130), (16, 16, 0)]
+OFFS = [(0,) * 8, (3, 5, 17, 2, 1, 7, 9, 11)]
+
+
+@pytest.mark.parametrize("m,n,k", GEMM_CASES)
+@pytest.mark.parametrize("offs", OFFS)
+def test_dgemm_nt(m, n, k, offs):
+    note("gemm_nt", m, n, k, offs)
+    ai, aj, bi, bj, ci, cj, di, dj = offs
+    rng = np.random.default_rng(m + 3 * n + 7 * k)
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (n, k))
+    C = rng.uniform(-1, 1, (m, n))
+    alpha, beta = 0.75, -1.5
+    sA = sentinel_mat(ai + m, aj + k)
+    sB = sentinel_mat(bi + n, bj + k)
+    sC = sentinel_mat(ci + m, cj + n)
+    sD = sentinel_mat(di + m, dj + n)
+    p.pack(dev(A), sA, ai, aj) if m * k else None
+    p.pack(dev(B), sB, bi, bj) if n * k else None
+    p.pack(dev(C), sC, ci, cj)
+    p.blasfeo_dgemm_nt(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj)
+    D = host(sD)
+    ref = oracle.dgemm_nt(A, B, C, alpha, beta)
+    assert_parity(D[di:, dj:], ref, max(m, n, k), "gemm_nt")
+    mask = np.ones_like(D, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(D[mask] == SENT)
+
+
+def test_dgemm_nt_integer_exact_and_in_place():
+    note("gemm_nt exact/in-place")
+    rng = np.random.default_rng(3)
+    A = rng.integers(-8, 9, (64, 64)).astype(float)
+    B = rng.integers(-8, 9, (64, 64)).astype(float)
+    C = rng.integers(-8, 9, (64, 64)).astype(float)
+    sA, sB, sC = mat(A), mat(B), mat(C)
+    p.blasfeo_dgemm_nt(64, 64, 64, 1.0, sA, 0, 0, sB, 0, 0, 1.0, sC, 0, 0, sC, 0, 0)  # C == D
+    assert np.array_equal(host(sC), C + A @ B.T)
+
+
+def test_workload_single_gemm_then_potrf():
+    """The single-instance workload: gemm_nt 64^3 then potrf_l of M M^T + 64 I."""
+    note("single workload")
+    s = synth.single(seed=0, n=64)
+    sA, sB, sC, sD = mat(s["A"]), mat(s["B"]), mat(s["C"]), p.DMat(64, 64)
+    p.blasfeo_dgemm_nt(64, 64, 64, 1.0, sA, 0, 0, sB, 0, 0, 1.0, sC, 0, 0, sD, 0, 0)
+    assert_parity(host(sD), oracle.dgemm_nt(s["A"], s["B"], s["C"]), 64, "gemm")
+    sS, sL = mat(s["S"]), sentinel_mat(64, 64)
+    info = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_info(64, sS, 0, 0, sL, 0, 0, info)
+    Lg = host(sL)
+    Lr, dAr, inf = oracle.dpotrf_l(s["S"])
+    assert int(info.item()) == 0 and inf == 0
+    assert_parity(np.tril(Lg), Lr, 64, "potrf")
+    assert np.all(np.triu(Lg, 1)[np.triu_indices(64, 1)] == SENT)
+    assert_parity(sL.dA()[:64].cpu().numpy(), dAr, 64, "dA")
+    assert sL.s.use_dA == 1
+
+
+# ------------------------------------------------------------------ syrk_ln
+
+@pytest.mark.parametrize("m,k", [(64, 64), (1, 1), (17, 5), (40, 32), (100, 70)])
+@pytest.mark.parametrize("off", [0, 5])
+def test_dsyrk_ln(m, k, off):
+    note("syrk_ln", m, k, off)
+    rng = np.random.default_rng(m * 7 + k)
+    A, B, C = rng.uniform(-1, 1, (m, k)), rng.uniform(-1, 1, (m, k)), rng.uniform(-1, 1, (m, m))
+    sA, sB = sentinel_mat(m + off, k + off), sentinel_mat(m + 2 * off, k)
+    sC, sD = sentinel_mat(m + off, m + off), sentinel_mat(m + off, m + 3 * off)
+    p.pack(dev(A), sA, off, off)
+    p.pack(dev(B), sB, 2 * off, 0)
+    p.pack(dev(C), sC, off, off)
+    p.blasfeo_dsyrk_ln(m, k, 1.5, sA, off, off, sB, 2 * off, 0, 0.5, sC, off, off, sD, off, 3 * off)
+    D = host(sD)
+    sub = D[off:, 3 * off:]
+    ref = oracle.dsyrk_ln(A, B, C, 1.5, 0.5)
+    assert_parity(np.tril(sub), ref, max(m, k), "syrk")
+    assert np.all(sub[np.triu_indices(m, 1)] == SENT)
+
+
+# ------------------------------------------------------------------ trsm_rltn
+
+@pytest.mark.parametrize("m,n", [(16, 64), (1, 1), (37, 50), (100, 17), (20, 130)])
+@pytest.mark.parametrize("offs", [(0, 0, 0, 0, 0, 0), (5, 3, 2, 9, 17, 1)])
+def test_dtrsm_rltn(m, n, offs):
+    note("trsm_rltn", m, n, offs)
+    ai, aj, bi, bj, di, dj = offs
+    rng = np.random.default_rng(m * 11 + n)
+    G = rng.standard_normal((n, n))
+    Lm = np.linalg.cholesky(G @ G.T / n + np.eye(n))
+    B = rng.standard_normal((m, n))
+    sA = sentinel_mat(ai + n, aj + n)
+    sB, sD = sentinel_mat(bi + m, bj + n), sentinel_mat(di + m, dj + n)
+    Lpoison = Lm + np.triu(np.full((n, n), np.nan), 1)  # upper part must not be read
+    p.pack(dev(Lpoison), sA, ai, aj)
+    p.pack(dev(B), sB, bi, bj)
+    p.blasfeo_dtrsm_rltn(m, n, 0.5, sA, ai, aj, sB, bi, bj, sD, di, dj)
+    D = host(sD)
+    assert_parity(D[di:, dj:], oracle.dtrsm_rltn(Lm, B, 0.5), max(m, n), "trsm")
+
+
+def test_dtrsm_rltn_integer_exact():
+    note("trsm exact")
+    L, _ = synth.small_integer_factor(48, seed=5, diag=(1.0, 2.0), off=1)
+    X = np.random.default_rng(6).integers(-5, 6, (16, 48)).astype(float)
+    sL, sB, sD = mat(L), mat(X @ L.T), p.DMat(16, 48)
+    p.blasfeo_dtrsm_rltn(16, 48, 1.0, sL, 0, 0, sB, 0, 0, sD, 0, 0)
+    assert np.array_equal(host(sD), X)
+
+
+# ------------------------------------------------------------------ potrf_l / syrk_potrf
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 31, 33, 64, 65, 100, 130, 256])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (5, 3, 17, 2)])
+def test_dpotrf_l(n, off):
+    note("potrf_l", n, off)
+    ci, cj, di, dj = off
+    rng = np.random.default_rng(n)
+    G = rng.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    Apoison = np.tril(A) + np.triu(np.full((n, n), np.nan), 1)  # only the lower part may be read
+    sC, sD = sentinel_mat(ci + n, cj + n), sentinel_mat(di + n, dj + n)
+    p.pack(dev(Apoison), sC, ci, cj)
+    info = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_info(n, sC, ci, cj, sD, di, dj, info)
+    D = host(sD)[di:, dj:]
+    Lr, dAr, inf = oracle.dpotrf_l(A)
+    assert int(info.item()) == 0
+    assert_parity(np.tril(D), Lr, n, "potrf")
+    assert np.all(D[np.triu_indices(n, 1)] == SENT)
+    assert_parity(sD.dA()[:n].cpu().numpy(), dAr, n, "dA")
+    assert sD.s.use_dA == int(di == 0 and dj == 0)
+
+
+@pytest.mark.parametrize("n", [16, 37, 64, 100])
+def test_dpotrf_l_small_integer_exact(n):
+    note("potrf exact", n)
+    L, A = synth.small_integer_factor(n, seed=n, diag=(1.0, 2.0), off=1)
+    sC, sD = mat(A), p.DMat(n, n)
+    p.blasfeo_dpotrf_l(n, sC, 0, 0, sD, 0, 0)
+    assert np.array_equal(np.tril(host(sD)), L)
+    assert np.array_equal(sD.dA()[:n].cpu().numpy(), 1.0 / np.diag(L))
+
+
+def test_dpotrf_l_in_place_identity_diagonal():
+    note("potrf identity/diag in place")
+    d = np.linspace(0.5, 9.0, 40)
+    s = mat(np.diag(d))
+    p.blasfeo_dpotrf_l(40, s, 0, 0, s, 0, 0)
+    out = host(s)
+    assert np.array_equal(np.diag(out), np.sqrt(d))
+    assert np.count_nonzero(np.tril(out, -1)) == 0
+
+
+@pytest.mark.parametrize("bad", [0, 7, 16, 39])
+def test_dpotrf_l_info_first_failing_pivot(bad):
+    note("potrf info", bad)
+    L, A = synth.small_integer_factor(40, seed=21, diag=(1.0, 2.0), off=1)
+    A = A.copy()
+    A[bad, bad] -= L[bad, bad] ** 2 + 1.0  # pivot of column `bad` becomes -1
+    Lr, _, inf = oracle.dpotrf_l(A)
+    assert inf == bad + 1
+    sC, sD = mat(A), p.DMat(40, 40)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_info(40, sC, 0, 0, sD, 0, 0, info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == bad + 1
+    assert np.array_equal(np.tril(host(sD))[:, :bad], L[:, :bad])
+
+
+@pytest.mark.parametrize("m,k", [(64, 64), (40, 32), (17, 3), (100, 50)])
+def test_dsyrk_dpotrf_ln(m, k):
+    note("syrk_potrf", m, k)
+    rng = np.random.default_rng(m + k)
+    A, B = rng.standard_normal((m, k)) / 4, rng.standard_normal((m, k)) / 4
+    G = rng.standard_normal((m, m))
+    M0 = G @ G.T + m * np.eye(m)
+    C = M0 - A @ B.T  # the lower part of C + A B^T is that of the SPD matrix M0
+    sA, sB, sC, sD = mat(A), mat(B), mat(C), p.DMat(m, m)
+    info = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dsyrk_dpotrf_ln_info(m, k, sA, 0, 0, sB, 0, 0, sC, 0, 0, sD, 0, 0, info)
+    Lr, dAr, inf = oracle.dsyrk_dpotrf_ln(A, B, C)
+    D = host(sD)
+    assert inf == 0 and int(info.item()) == 0
+    assert_parity(np.tril(D), Lr, m, "syrk_potrf")
+
+
+# ------------------------------------------------------------------ uniform batches (generic kernels)
+
+def test_batched_generic_routines():
+    note("batched generic")
+    batch, m, n, k = 33, 20, 36, 12
+    rng = np.random.default_rng(9)
+    A, B, C = rng.uniform(-1, 1, (batch, m, k)), rng.uniform(-1, 1, (batch, n, k)), rng.uniform(-1, 1, (batch, m, n))
+    sA, sB, sC = p.pack_batch(dev(A)), p.pack_batch(dev(B)), p.pack_batch(dev(C))
+    sD = p.DMatBatch(batch, m, n)
+    p.blasfeo_hip_dgemm_nt_batched(batch, m, n, k, 1.0, sA, 0, 0, sB, 0, 0, -1.0, sC, 0, 0, sD, 0, 0)
+    torch.cuda.synchronize()
+    D = p.unpack_batch(sD).cpu().numpy()
+    for b in range(batch):
+        assert_parity(D[b], oracle.dgemm_nt(A[b], B[b], C[b], 1.0, -1.0), k, f"gemm b={b}")
+    G = rng.standard_normal((batch, m, m))
+    S = G @ np.swapaxes(G, 1, 2) + m * np.eye(m)
+    sS, sL = p.pack_batch(dev(S)), p.DMatBatch(batch, m, m, fill=0.0)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_batched(batch, m, sS, 0, 0, sL, 0, 0, info)
+    torch.cuda.synchronize()
+    L = p.unpack_batch(sL).cpu().numpy()
+    dA = sL.dA()[:, :m].cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    for b in range(batch):
+        Lr, dAr, _ = oracle.dpotrf_l(S[b])
+        assert_parity(np.tril(L[b]), Lr, m, f"potrf b={b}")
+        assert_parity(dA[b], dAr, m, f"dA b={b}")
+    X = rng.standard_normal((batch, 5, m))
+    sX, sY = p.pack_batch(dev(X)), p.DMatBatch(batch, 5, m)
+    p.blasfeo_hip_dtrsm_rltn_batched(batch, 5, m, 2.0, sL, 0, 0, sX, 0, 0, sY, 0, 0)
+    torch.cuda.synchronize()
+    Y = p.unpack_batch(sY).cpu().numpy()
+    for b in range(batch):
+        assert_parity(Y[b], oracle.dtrsm_rltn(np.tril(L[b]), X[b], 2.0), m, f"trsm b={b}")
