@@ -52,12 +52,8 @@ __device__ __forceinline__ constexpr int tix(int j, int i) {
 // register of a T-tile or one MFMA fragment is a single 512-byte wave
 // transaction.
 template <int NB, bool FULL>
-__global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
-  __shared__ DiagLds lds[FW];
-  const int w = threadIdx.x >> 6;
-  const long long b = (long long)blockIdx.x * FW + w;
-  if (b >= a.batch) return;
-  DiagLds &s = lds[w];
+__device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
+                                               DiagLds &s, double (*zl)[256]) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
   const int m = FULL ? 16 * NB : a.m;
@@ -67,6 +63,7 @@ __global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
   const brsrc rA = make_rsrc(a.A + b * a.sA, 8 * a.sA);
   const brsrc rQ = make_rsrc(a.Q + b * a.sQ, 8 * a.sQ);
   const brsrc rL = make_rsrc(a.L + b * a.sL, 8 * a.sL);  // L panels and dA
+  const brsrc rX = make_rsrc(a.X + b * a.sX, 8 * a.sX);
   const int dA_off = (int)(8 * (a.dA - a.L));
   const int pQ = 8 * 16 * a.cnQ, pA = 8 * 16 * a.cnA, pL = 8 * 16 * a.cnL;
 
@@ -84,6 +81,23 @@ __global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
         T[tix<NB>(j, i)][r] = ok ? x : 0.0;
       }
     }
+  }
+
+  // right-hand sides Z(j) = E(:, 16j:16j+16)^T, staged in LDS: they are
+  // read-modify-written once per block row, so they need no registers
+  // during the factorization.
+  const bool has_rhs = a.nrhs > 0;
+  if (has_rhs) {
+    const brsrc rE = make_rsrc(a.E + b * a.sE, 8 * a.sE);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = 16 * j + g + 4 * r;
+        const bool ok = FULL || (c < a.nrhs && col < m);
+        const double x = bload(rE, vo, 8 * (256 * j + 64 * r));
+        zl[j][64 * r + l] = ok ? x : 0.0;
+      }
   }
 
   // syrk: T(j,i) += A_j A_i^T, one MFMA per block pair per 4-wide k-step.
@@ -125,24 +139,6 @@ __global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
     }
   }
 
-  // right-hand sides: Z(j) = E(:, 16j:16j+16)^T
-  d4 Z[NB];
-  const bool has_rhs = a.nrhs > 0;
-  brsrc rE, rX;
-  if (has_rhs) {
-    rE = make_rsrc(a.E + b * a.sE, 8 * a.sE);
-    rX = make_rsrc(a.X + b * a.sX, 8 * a.sX);
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = 16 * j + g + 4 * r;
-        const bool ok = FULL || (c < a.nrhs && col < m);
-        const double x = bload(rE, vo, 8 * (256 * j + 64 * r));
-        Z[j][r] = ok ? x : 0.0;
-      }
-  }
-
   int info = 0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -170,12 +166,17 @@ __global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
         if (FULL || (row < m && col < m)) bstore(rL, vo, i * pL + 8 * (256 * j + 64 * r), Ti[r]);
       }
     }
+    d4 Y;
     if (has_rhs) {
-      Z[j] = mfma_tn(V, Z[j], zero4());
+      // Y(j) = V^T Z(j), the block of X = E L^-T for columns 16j..16j+15
+      d4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[r] = zl[j][64 * r + l];
+      Y = mfma_tn(V, z, zero4());
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = 16 * j + g + 4 * r;
-        if (FULL || (c < a.nrhs && col < m)) bstore(rX, vo, 8 * (256 * j + 64 * r), Z[j][r]);
+        if (FULL || (c < a.nrhs && col < m)) bstore(rX, vo, 8 * (256 * j + 64 * r), Y[r]);
       }
     }
     // trailing downdate of the remaining block rows and right-hand sides
@@ -185,10 +186,30 @@ __global__ __launch_bounds__(64 * FW) void k_syrk_potrf_trsm(FusedArgs a) {
 #pragma unroll
       for (int i = q; i < NB; ++i)
         T[tix<NB>(q, i)] = mfma_tn(nu, T[tix<NB>(j, i)], T[tix<NB>(q, i)]);
-      if (has_rhs) Z[q] = mfma_tn(nu, Z[j], Z[q]);
+      if (has_rhs) {
+        d4 z;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[r] = zl[q][64 * r + l];
+        z = mfma_tn(nu, Y, z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zl[q][64 * r + l] = z[r];
+      }
     }
   }
   if (a.info && l == 0) a.info[b] = info;
+
+}
+
+// One wavefront per instance; the occupancy hint keeps the register
+// footprint of the largest variant at three waves per SIMD.
+template <int NB, bool FULL>
+__global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(3)))
+void k_syrk_potrf_trsm(FusedArgs a) {
+  __shared__ DiagLds lds[FW];
+  __shared__ double zl[FW][NB][256];  // right-hand-side blocks, T-tile order
+  const int w = threadIdx.x >> 6;
+  const long long b = (long long)blockIdx.x * FW + w;
+  if (b < a.batch) fused_instance<NB, FULL>(a, b, lds[w], zl[w]);
 }
 
 template <int NB>
