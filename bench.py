@@ -72,6 +72,43 @@ def uniform_counts(n=64, k=64, nrhs=16):
     return flops, byts
 
 
+def uneven_counts(ns):
+    """Algorithmic flops (potrf + potrs, 1 rhs) and bytes (A lower in, L lower
+    out, b in, x out, dA out) of the uneven batch."""
+    n = np.asarray(ns, dtype=np.float64)
+    flops = float(np.sum(flops_potrf(n) + 2 * n * n))
+    byts = float(np.sum(8 * (n * (n + 1) + 3 * n)))
+    return flops, byts
+
+
+def bench_uneven(p, synth, torch, batch=65536, reps=5):
+    """The uneven workload: 65536 SPD solves, n = 8*U{1..32}, 1 rhs, through
+    a plan (size classes, autotuned launch shapes, captured hipGraph)."""
+    ns = synth.uneven_sizes(batch, seed=2)
+    plan = p.VbPlan(ns, 1)
+    A, L = plan.mat_arena(), plan.mat_arena(fill=0.0)
+    B, X = plan.vec_arena(), plan.vec_arena()
+    classes = synth.uneven_batch_device(ns, seed=2)
+    for n, (idx, An, bn) in classes.items():
+        plan.pack_class(n, idx, An, A)
+        plan.scatter_rhs(n, idx, bn, B)
+    del classes
+    torch.cuda.empty_cache()
+    info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    plan.autotune(A, L, B, X, info)
+    stream = torch.cuda.current_stream()
+    _, per = time_events(lambda: plan.solve(A, L, B, X, info), reps, 2, stream)
+    ms = float(np.median(per))
+    fl, by = uneven_counts(ns)
+    bad = int((info != 0).sum().item())
+    out = {"uneven_ms": round(ms, 3), "uneven_gflops": round(fl / ms / 1e6, 1),
+           "uneven_solves_per_s": round(batch / ms * 1e3, 1), "uneven_gbs": round(by / ms / 1e6, 1),
+           "uneven_failed": bad, "uneven_config": [int(x) for x in plan.config()]}
+    del A, L, B, X, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_events(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -114,6 +151,7 @@ def main():
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true", help="time only the uniform-batch workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -175,6 +213,10 @@ def main():
         "uniform_kernel_ms_min": round(float(np.min(per)), 4),
         "uniform_failed_instances": bad,
     }
+
+    if not args.no_extra:
+        print("[bench] uneven batch (65536 solves)", file=sys.stderr, flush=True)
+        extra.update(bench_uneven(p, synth, torch))
 
     if args.calib_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

@@ -210,6 +210,16 @@ int blasfeo_hip_unpack_dmat_batched(int batch, int m, int n,
                                     int aj, double *B, int ldb,
                                     long long strideB, void *stream);
 
+/* Pack (to_panel = 1) or unpack (0) `count` m-by-n column-major matrices
+ * (instance b at A + b*strideA, leading dimension lda) to/from panel-major
+ * chunks (panel length round_up(n, 4)) starting at arena + dst_off[b]
+ * doubles; dst_off is a device array.  Used to fill the arenas of a plan
+ * size class by size class. */
+int blasfeo_hip_pack_dmat_indexed(int count, int m, int n, const double *A,
+                                  int lda, long long strideA,
+                                  const long long *dst_off, double *arena,
+                                  int to_panel, void *stream);
+
 int blasfeo_hip_dgemm_nt_batched(int batch, int m, int n, int k,
                                  double alpha,
                                  const struct blasfeo_dmat *sA, int ai,
@@ -254,6 +264,57 @@ int blasfeo_hip_dsyrk_dpotrf_trsm_batched(int batch, int m, int k, int nrhs,
                                           const struct blasfeo_dmat *sL,
                                           const struct blasfeo_dmat *sX,
                                           int *info, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Uneven batches: plans.  A plan is created once for a list of orders and
+ * executed many times (the embedded-optimization pattern of §2: the same
+ * structure is re-solved at every sampling time).
+ *
+ * Operation per instance i (potrf_l then the forward/back substitution of
+ * trsv_lnn/trsv_ltn, §5.2.2 and Appendix A.3):
+ *     L_i = chol(A_i),   X_i = A_i^{-1} B_i = L_i^{-T} L_i^{-1} B_i.
+ * Memory layout (fixed by the plan, queried with blasfeo_hip_plan_layout):
+ *   - A_i (lower part read) is a blasfeo_dmat(n_i, n_i) chunk at byte offset
+ *     mat_off[i] of a matrix arena of mat_bytes bytes; L_i (lower part and
+ *     its dA written) lives at the same offset of a second arena.
+ *   - B_i and X_i are column-major n_i x nrhs blocks, leading dimension
+ *     round_up(n_i, 16), at byte offset vec_off[i] of two vector arenas of
+ *     vec_bytes bytes.
+ * The plan sorts the instances into size classes (n <= 16, 32, 48, 64: one
+ * wavefront per instance; n > 64: one workgroup per instance, largest
+ * first), records one kernel launch per class into a hipGraph on the first
+ * execution with a given set of pointers, and replays that graph afterwards.
+ * Plan creation allocates a small device table (orders, offsets, class
+ * lists) with hipMalloc; execution allocates nothing.
+ * ---------------------------------------------------------------------- */
+typedef struct blasfeo_hip_plan blasfeo_hip_plan;
+
+/* batch >= 0 instances of orders n_host[i] in 1..512, nrhs in 0..16.
+ * Returns 0 or -i / HIP error; *plan receives the plan. */
+int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
+                                    blasfeo_hip_plan **plan);
+/* Byte offsets of every instance (arrays of `batch` entries, may be NULL)
+ * and the arena sizes. */
+int blasfeo_hip_plan_layout(const blasfeo_hip_plan *plan, long long *mat_off,
+                            long long *vec_off, long long *mat_bytes,
+                            long long *vec_bytes);
+/* Factor and solve every instance (device arenas A, L, B, X; info is a
+ * device array of `batch` ints, may be NULL).  Asynchronous on `stream`. */
+int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *plan, const void *A,
+                               void *L, const void *B, void *X, int *info,
+                               void *stream);
+/* Times every candidate launch configuration of every size class on the
+ * given data (which is overwritten like an execution) and keeps the fastest
+ * (waves per workgroup); synchronizes the stream. */
+int blasfeo_hip_plan_autotune(blasfeo_hip_plan *plan, const void *A, void *L,
+                              const void *B, void *X, int *info,
+                              void *stream);
+/* on = 0 executes with plain launches instead of the captured graph. */
+int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
+/* Writes the chosen configuration of every size class to cfg_out (may be
+ * NULL) and returns the number of classes. */
+int blasfeo_hip_plan_config(const blasfeo_hip_plan *plan, int *cfg_out);
+void blasfeo_hip_plan_destroy(blasfeo_hip_plan *plan);
 
 #ifdef __cplusplus
 }

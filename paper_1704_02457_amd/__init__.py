@@ -70,6 +70,14 @@ _SIGS = {
     "blasfeo_hip_dtrsm_rltn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
+    "blasfeo_hip_pack_dmat_indexed": (_i, [_i, _i, _i, _p, _i, _ll, _p, _p, _i, _p]),
+    "blasfeo_hip_dposv_vbatched_plan": (_i, [_i, _p, _i, ctypes.POINTER(_p)]),
+    "blasfeo_hip_plan_layout": (_i, [_p, _p, _p, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
+    "blasfeo_hip_dposv_vbatched": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
+    "blasfeo_hip_plan_config": (_i, [_p, _p]),
+    "blasfeo_hip_plan_destroy": (None, [_p]),
 }
 
 
@@ -148,6 +156,7 @@ class DMat:
         if storage is None:
             storage = torch.empty(max(ms, 256) // 8, dtype=torch.float64, device=device)
         self.buf = storage
+        self.off = offset_bytes // 8
         lib().blasfeo_create_dmat(m, n, ctypes.byref(self.s), ctypes.c_void_p(storage.data_ptr() + offset_bytes))
         self.m, self.n = m, n
 
@@ -161,10 +170,10 @@ class DMat:
 
     def panels(self):
         """The panel storage as a flat float64 tensor view (pm*16*cn)."""
-        return self.buf[: self.s.pm * PS * self.s.cn]
+        return self.buf[self.off: self.off + self.s.pm * PS * self.s.cn]
 
     def dA(self):
-        off = self.s.pm * PS * self.s.cn
+        off = self.off + self.s.pm * PS * self.s.cn
         return self.buf[off: off + max(self.m, self.n)]
 
 
@@ -319,3 +328,105 @@ def blasfeo_hip_dsyrk_dpotrf_trsm_batched(batch, m, k, nrhs, sA, sQ, sE, sL, sX,
     return check(lib().blasfeo_hip_dsyrk_dpotrf_trsm_batched(
         batch, m, k, nrhs, sA.ref if sA is not None else None, sQ.ref, sE.ref if sE is not None else None,
         sL.ref, sX.ref if sX is not None else None, _ptr(info), _stream(stream)))
+
+
+# ------------------------------------------------------------------ uneven batches (plans)
+
+class VbPlan:
+    """Plan of an uneven batch of SPD solves (blasfeo_hip_dposv_vbatched_plan).
+
+    Arenas are flat float64 device tensors; instance i's matrix chunk starts
+    at element moff[i] of a matrix arena, its n_i x nrhs right-hand sides
+    (column-major, leading dimension round_up(n_i, 16)) at element voff[i] of
+    a vector arena.
+    """
+
+    def __init__(self, ns, nrhs):
+        import numpy as np
+        self.ns = np.asarray(ns, dtype=np.int32)
+        self.nrhs = int(nrhs)
+        self.handle = ctypes.c_void_p()
+        arr = np.ascontiguousarray(self.ns)
+        check(lib().blasfeo_hip_dposv_vbatched_plan(len(arr), arr.ctypes.data_as(ctypes.c_void_p), self.nrhs,
+                                                    ctypes.byref(self.handle)))
+        self.moff = np.zeros(max(len(arr), 1), dtype=np.int64)
+        self.voff = np.zeros(max(len(arr), 1), dtype=np.int64)
+        mb, vb = ctypes.c_longlong(), ctypes.c_longlong()
+        check(lib().blasfeo_hip_plan_layout(self.handle, self.moff.ctypes.data_as(ctypes.c_void_p),
+                                            self.voff.ctypes.data_as(ctypes.c_void_p), ctypes.byref(mb),
+                                            ctypes.byref(vb)))
+        self.moff, self.voff = self.moff[: len(arr)] // 8, self.voff[: len(arr)] // 8
+        self.mat_bytes, self.vec_bytes = mb.value, vb.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.blasfeo_hip_plan_destroy(h)
+            self.handle = ctypes.c_void_p()
+
+    def mat_arena(self, fill=None, device="cuda"):
+        torch = _torch()
+        n = max(self.mat_bytes // 8, 32)
+        if fill is None:
+            return torch.empty(n, dtype=torch.float64, device=device)
+        return torch.full((n,), fill, dtype=torch.float64, device=device)
+
+    def vec_arena(self, fill=0.0, device="cuda"):
+        torch = _torch()
+        return torch.full((max(self.vec_bytes // 8, 32),), fill, dtype=torch.float64, device=device)
+
+    def dmat(self, arena, i):
+        """DMat view of instance i inside a matrix arena."""
+        n = int(self.ns[i])
+        return DMat(n, n, storage=arena, offset_bytes=int(self.moff[i]) * 8)
+
+    def rhs(self, arena, i):
+        """(n_i, nrhs) view of instance i's block inside a vector arena."""
+        n = int(self.ns[i])
+        ld = (n + 15) // 16 * 16
+        o = int(self.voff[i])
+        return arena[o: o + ld * max(self.nrhs, 1)].view(max(self.nrhs, 1), ld)[:, :n].t()
+
+    def pack_class(self, n, idx, A, arena):
+        """Pack the (count, n, n) tensor A of the instances `idx` (all of order n)."""
+        torch = _torch()
+        At = A.transpose(1, 2).contiguous()
+        off = torch.as_tensor(self.moff[idx], dtype=torch.int64, device=A.device)
+        check(lib().blasfeo_hip_pack_dmat_indexed(len(idx), n, n, At.data_ptr(), n, n * n, off.data_ptr(),
+                                                  arena.data_ptr(), 1, _stream()))
+
+    def rhs_index(self, n, idx):
+        """(count, nrhs, n) int64 element indices of the right-hand sides of
+        the instances `idx` (all of order n) inside a vector arena."""
+        torch = _torch()
+        ld = (n + 15) // 16 * 16
+        base = torch.as_tensor(self.voff[idx], dtype=torch.int64, device="cuda")
+        c = torch.arange(max(self.nrhs, 1), device="cuda", dtype=torch.int64)[:, None] * ld
+        r = torch.arange(n, device="cuda", dtype=torch.int64)[None, :]
+        return base[:, None, None] + (c + r)[None]
+
+    def scatter_rhs(self, n, idx, Bn, arena):
+        """Write the (count, n, nrhs) right-hand sides of instances `idx`."""
+        arena[self.rhs_index(n, idx)] = Bn.reshape(len(idx), n, -1).transpose(1, 2).to(arena.dtype)
+
+    def gather_rhs(self, n, idx, arena):
+        """(count, n, nrhs) blocks of instances `idx` from a vector arena."""
+        return arena[self.rhs_index(n, idx)].transpose(1, 2)
+
+    def solve(self, A, L, B, X, info=None, stream=None):
+        return check(lib().blasfeo_hip_dposv_vbatched(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
+                                                      _ptr(info), _stream(stream)))
+
+    def autotune(self, A, L, B, X, info=None, stream=None):
+        return check(lib().blasfeo_hip_plan_autotune(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
+                                                     _ptr(info), _stream(stream)))
+
+    def set_graph(self, on):
+        return check(lib().blasfeo_hip_plan_set_graph(self.handle, 1 if on else 0))
+
+    def config(self):
+        import numpy as np
+        k = lib().blasfeo_hip_plan_config(self.handle, None)
+        out = np.zeros(k, dtype=np.int32)
+        lib().blasfeo_hip_plan_config(self.handle, out.ctypes.data_as(ctypes.c_void_p))
+        return out

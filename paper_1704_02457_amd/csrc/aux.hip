@@ -50,6 +50,26 @@ static int launch_pack(int batch, int m, int n, const double *A, int lda,
   return launch_status();
 }
 
+// Pack/unpack of `count` m x n column-major matrices (instance b at A +
+// b*sa) to/from panel-major chunks at arbitrary offsets of an arena.
+__global__ void k_pack_indexed(int count, int m, int n, const double *__restrict__ A,
+                               int lda, long long sa, const long long *__restrict__ off,
+                               double *__restrict__ arena, int cn, int to_panel) {
+  const long long per = (long long)m * n;
+  const long long total = per * count;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+       t < total; t += (long long)gridDim.x * blockDim.x) {
+    const long long b = t / per, e = t - b * per;
+    const int i = (int)(e % m), j = (int)(e / m);
+    const long long po = off[b] + pm_off(i, j, cn);
+    const long long co = b * sa + (long long)i + (long long)j * lda;
+    if (to_panel)
+      arena[po] = A[co];
+    else
+      ((double *)A)[co] = arena[po];
+  }
+}
+
 }  // namespace bh
 
 using namespace bh;
@@ -259,6 +279,29 @@ int blasfeo_hip_unpack_dmat_batched(int batch, int m, int n,
   if (strideB < 0) return -9;
   return launch_pack(batch, m, n, B, ldb, strideB, sA->pA, sA->cn, ai, aj,
                      batch_stride(sA), 0, (hipStream_t)stream);
+}
+
+int blasfeo_hip_pack_dmat_indexed(int count, int m, int n, const double *A,
+                                  int lda, long long strideA,
+                                  const long long *dst_off, double *arena,
+                                  int to_panel, void *stream) {
+  if (count < 0) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!A && count > 0 && m > 0 && n > 0) return -4;
+  if (lda < (m > 1 ? m : 1)) return -5;
+  if (strideA < 0) return -6;
+  if (!dst_off && count > 0) return -7;
+  if (!arena && count > 0) return -8;
+  if (count == 0 || m == 0 || n == 0) return 0;
+  const int cn = (n + 3) / 4 * 4;
+  long long total = (long long)m * n * count;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_pack_indexed, dim3((unsigned)blocks), dim3(256), 0,
+                     (hipStream_t)stream, count, m, n, A, lda, strideA, dst_off,
+                     arena, cn, to_panel);
+  return launch_status();
 }
 
 }  // extern "C"

@@ -50,6 +50,10 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 __device__ __forceinline__ d4 zero4() { return (d4){0.0, 0.0, 0.0, 0.0}; }
 
+// Index of the upper block (j, i), j <= i, in a column-packed list of the
+// upper block triangle (U = L^T view of a lower factor).
+__host__ __device__ constexpr int tix_up(int j, int i) { return i * (i + 1) / 2 + j; }
+
 // acc += X^T * Y for T-tiles X, Y (four chained MFMAs).
 __device__ __forceinline__ d4 mfma_tn(const d4 &X, const d4 &Y, d4 acc) {
   acc = mfma(X[0], Y[0], acc);
@@ -127,6 +131,36 @@ __device__ __forceinline__ d4 load_tileT(const View &v, int i0, int j0,
     t[r] = x;
   }
   return t;
+}
+
+// T-tile holding the block S[i0:i0+16, j0:j0+16] itself (not transposed):
+// register r of lane (c, g) = S[i0 + g + 4r][j0 + c].  Zero outside S.
+__device__ __forceinline__ d4 load_tileN(const View &v, int i0, int j0) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + g + 4 * r, j = j0 + c;
+    double x = 0.0;
+    if (i < v.rows && j < v.cols) x = v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
+    t[r] = x;
+  }
+  return t;
+}
+
+// Transpose of a T-tile through 16x17 doubles of wave-private LDS.
+__device__ __forceinline__ d4 transpose_tile(const d4 &x, double *tr) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tr[(g + 4 * r) * 17 + c] = x[r];
+  wave_sync();
+  d4 y;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] = tr[c * 17 + g + 4 * r];
+  wave_sync();
+  return y;
 }
 
 // Stores the T-tile t (holding the transpose of a block) into
@@ -267,7 +301,8 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
 // pivot row of U and of W go through LDS once per pivot.  V is W^T (one LDS
 // transpose at the end).
 __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
-                                                    DiagLds &s) {
+                                                    DiagLds &s,
+                                                    d4 *Wout = nullptr) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
   int info = 0;
@@ -314,6 +349,7 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
       }
     }
   }
+  if (Wout) *Wout = W;  // W = L^{-1} = V^T, itself a T-tile
   // V = W^T through a padded LDS transpose
 #pragma unroll
   for (int r = 0; r < 4; ++r) s.tr[(g + 4 * r) * 17 + c] = W[r];

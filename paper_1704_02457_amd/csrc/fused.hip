@@ -41,10 +41,6 @@ struct FusedArgs {
   int *info;
 };
 
-template <int NB>
-__device__ __forceinline__ constexpr int tix(int j, int i) {
-  return i * (i + 1) / 2 + j;  // upper block (j <= i), column-packed
-}
 
 // FULL: m == 16*NB, k % 16 == 0 and nrhs in {0, 16}: no masking at all.
 // All accesses go through buffer descriptors of the instance's chunks; the
@@ -78,7 +74,7 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
         const int row = 16 * i + c, col = 16 * j + g + 4 * r;
         const bool ok = (FULL || (row < m && col < m)) && (i != j || c >= g + 4 * r);
         const double x = bload(rQ, vo, i * pQ + 8 * (256 * j + 64 * r));
-        T[tix<NB>(j, i)][r] = ok ? x : 0.0;
+        T[tix_up(j, i)][r] = ok ? x : 0.0;
       }
     }
   }
@@ -126,7 +122,7 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
         for (int i = 0; i < NB; ++i)
 #pragma unroll
           for (int j = 0; j <= i; ++j)
-            T[tix<NB>(j, i)] = mfma(f[t][j], f[t][i], T[tix<NB>(j, i)]);
+            T[tix_up(j, i)] = mfma(f[t][j], f[t][i], T[tix_up(j, i)]);
     };
     if (nch > 0) load_chunk(fa, 0);
     for (int ch = 0; ch < nch; ch += 2) {
@@ -143,7 +139,7 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int nv = FULL ? 16 : min(16, m - 16 * j);
-    d4 &D = T[tix<NB>(j, j)];
+    d4 &D = T[tix_up(j, j)];
     if (!FULL && nv < 16) pad_identity(D, nv);
     d4 V;
     const int inf = potrf_inv_tile_upper(D, V, s);
@@ -158,7 +154,7 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
     }
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) {
-      d4 &Ti = T[tix<NB>(j, i)];
+      d4 &Ti = T[tix_up(j, i)];
       Ti = mfma_tn(V, Ti, zero4());
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -182,10 +178,10 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
     // trailing downdate of the remaining block rows and right-hand sides
 #pragma unroll
     for (int q = j + 1; q < NB; ++q) {
-      const d4 nu = neg4(T[tix<NB>(j, q)]);
+      const d4 nu = neg4(T[tix_up(j, q)]);
 #pragma unroll
       for (int i = q; i < NB; ++i)
-        T[tix<NB>(q, i)] = mfma_tn(nu, T[tix<NB>(j, i)], T[tix<NB>(q, i)]);
+        T[tix_up(q, i)] = mfma_tn(nu, T[tix_up(j, i)], T[tix_up(q, i)]);
       if (has_rhs) {
         d4 z;
 #pragma unroll

@@ -1,0 +1,629 @@
+// Uneven batches of SPD solves A_i X_i = B_i (potrf_l + forward/back
+// substitution), driven by a host-side plan: instances are bucketed by order,
+// every bucket is one launch of a kernel specialised for its size class, the
+// launches are captured once into a hipGraph and replayed.
+//
+//   n <= 64  : one wavefront per instance, the whole factor register
+//              resident (the fused kernel's scheme with the right-hand sides
+//              staged in LDS); forward substitution interleaved with the
+//              factorization, back substitution on the register tiles.
+//   n >  64  : one workgroup per instance, left-looking over block columns
+//              (each block of L is produced once: gemm downdate, then the
+//              diagonal subroutine or the solve with the diagonal block's
+//              inverse -- §4.6), forward substitution fused into the
+//              diagonal step, back substitution at the end; instances in
+//              longest-first order.
+//
+// Layout (fixed by the plan): instance i's matrix is a blasfeo_dmat(n_i, n_i)
+// chunk; its right-hand sides are a column-major n_i x nrhs block with leading
+// dimension round_up(n_i, 16).  The factor L (with its dA) goes to a second
+// arena of the same layout, the solutions to a second vector arena.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace bh {
+
+struct VbArgs {
+  const int *ids;          // instances of this bucket
+  int count;
+  const int *n;            // order of every instance
+  const long long *moff;   // matrix chunk offsets (doubles)
+  const long long *voff;   // right-hand-side block offsets (doubles)
+  const double *A;
+  double *L;
+  const double *B;
+  double *X;
+  int nrhs;
+  int *info;
+};
+
+__device__ __forceinline__ int cn_of(int n) { return (n + 3) & ~3; }
+__device__ __forceinline__ int ld_of(int n) { return (n + 15) & ~15; }
+
+// Right-hand-side block j as a T-tile: logical (row p, column c) =
+// B[16j + p][c] for c < nrhs, p < n (zero elsewhere).
+__device__ __forceinline__ d4 load_rhs(const double *Bb, int ld, int n,
+                                       int nrhs, int j) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  d4 z;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int p = 16 * j + g + 4 * r;
+    z[r] = (c < nrhs && p < n) ? Bb[(long long)c * ld + p] : 0.0;
+  }
+  return z;
+}
+
+__device__ __forceinline__ void store_rhs(double *Xb, int ld, int n, int nrhs,
+                                          int j, const d4 &x) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int p = 16 * j + g + 4 * r;
+    if (c < nrhs && p < n) Xb[(long long)c * ld + p] = x[r];
+  }
+}
+
+// ---------------------------------------------------------------- n <= 64
+
+template <int NB, int VW>
+__global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
+  __shared__ DiagLds lds[VW];
+  __shared__ double zl[VW][NB][256];  // right-hand sides, then y, then x
+  const int w = threadIdx.x >> 6;
+  const int t = blockIdx.x * VW + w;
+  if (t >= a.count) return;
+  DiagLds &s = lds[w];
+  const int id = a.ids[t];
+  const int n = a.n[id];
+  const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  constexpr int NT = NB * (NB + 1) / 2;
+  const double *Ab = a.A + a.moff[id];
+  double *Lb = a.L + a.moff[id];
+  const long long panel_doubles = (long long)pm * 16 * cn;
+  const brsrc rA = make_rsrc(Ab, 8 * panel_doubles);
+  const brsrc rL = make_rsrc(Lb, 8 * (panel_doubles + n));
+  const int vo = 8 * l, pS = 8 * 16 * cn;
+
+  d4 T[NT];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + c, col = 16 * j + g + 4 * r;
+        const bool ok = row < n && col < n && (i != j || c >= g + 4 * r);
+        const double x = ok ? bload(rA, vo, i * pS + 8 * (256 * j + 64 * r)) : 0.0;
+        T[tix_up(j, i)][r] = x;
+      }
+  const bool has_rhs = a.nrhs > 0;
+  if (has_rhs) {
+    const double *Bb = a.B + a.voff[id];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const d4 z = load_rhs(Bb, ld, n, a.nrhs, j);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zl[w][j][64 * r + l] = z[r];
+    }
+  }
+
+  int info = 0;
+  d4 Wk[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int nv = min(16, n - 16 * j);
+    d4 &D = T[tix_up(j, j)];
+    if (nv < 16) pad_identity(D, nv);
+    d4 V;
+    const int inf = potrf_inv_tile_upper(D, V, s, &Wk[j]);
+    if (inf && info == 0) info = 16 * j + inf;
+    if (l < nv) bstore(rL, vo, 8 * (int)(panel_doubles + 16 * j), s.inv[l]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * j + c, col = 16 * j + g + 4 * r;
+      if (row < n && col < n && c >= g + 4 * r) bstore(rL, vo, j * pS + 8 * (256 * j + 64 * r), D[r]);
+    }
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      d4 &Ti = T[tix_up(j, i)];
+      Ti = mfma_tn(V, Ti, zero4());
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + c, col = 16 * j + g + 4 * r;
+        if (row < n && col < n) bstore(rL, vo, i * pS + 8 * (256 * j + 64 * r), Ti[r]);
+      }
+    }
+    d4 y;
+    if (has_rhs) {  // forward substitution: y(j) = V^T z(j)
+      d4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[r] = zl[w][j][64 * r + l];
+      y = mfma_tn(V, z, zero4());
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zl[w][j][64 * r + l] = y[r];
+    }
+#pragma unroll
+    for (int q = j + 1; q < NB; ++q) {
+      const d4 nu = neg4(T[tix_up(j, q)]);
+#pragma unroll
+      for (int i = q; i < NB; ++i)
+        T[tix_up(q, i)] = mfma_tn(nu, T[tix_up(j, i)], T[tix_up(q, i)]);
+      if (has_rhs) {
+        d4 z;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[r] = zl[w][q][64 * r + l];
+        z = mfma_tn(nu, y, z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zl[w][q][64 * r + l] = z[r];
+      }
+    }
+  }
+  if (has_rhs) {
+    // back substitution: x(j) = V_j (y(j) - sum_{i>j} U(j,i) x(i)), with
+    // U(j,i) x(i) = (U(j,i)^T)^T x(i) and V_j = W_j^T
+    double *Xb = a.X + a.voff[id];
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j) {
+      d4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = zl[w][j][64 * r + l];
+#pragma unroll
+      for (int i = j + 1; i < NB; ++i) {
+        const d4 ut = transpose_tile(T[tix_up(j, i)], s.tr);
+        d4 xi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xi[r] = zl[w][i][64 * r + l];
+        acc = mfma_tn(neg4(ut), xi, acc);
+      }
+      const d4 x = mfma_tn(Wk[j], acc, zero4());
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zl[w][j][64 * r + l] = x[r];
+      store_rhs(Xb, ld, n, a.nrhs, j, x);
+    }
+  }
+  if (a.info && l == 0) a.info[id] = info;
+}
+
+// ---------------------------------------------------------------- n > 64
+
+// Dynamic LDS of k_vb_large: W_j tiles (nbmax x 256), compact y/x blocks
+// (nbmax x 16 x nrhs), the current V (256), diagonal scratch.
+__device__ __forceinline__ void save_compact(double *buf, const d4 &y, int nrhs) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  if (c < nrhs) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) buf[(g + 4 * r) * nrhs + c] = y[r];
+  }
+}
+
+__device__ __forceinline__ d4 load_compact(const double *buf, int nrhs) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  d4 y;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] = (c < nrhs) ? buf[(g + 4 * r) * nrhs + c] : 0.0;
+  return y;
+}
+
+// Gemm downdate of the upper block T(j,i) of the transposed factor:
+//   acc -= sum_{q<j} U(q,j)^T U(q,i),  U(q,x) read back from L,
+// UNR block pairs per round so that 2*UNR tile loads are in flight.
+template <int UNR>
+__device__ __forceinline__ d4 downdate(const View &L, int j, int i, d4 acc) {
+  int q = 0;
+  for (; q + UNR <= j; q += UNR) {
+    d4 uj[UNR], ui[UNR];
+#pragma unroll
+    for (int t = 0; t < UNR; ++t) {
+      uj[t] = load_tileT(L, 16 * j, 16 * (q + t), false);
+      ui[t] = i == j ? uj[t] : load_tileT(L, 16 * i, 16 * (q + t), false);
+    }
+#pragma unroll
+    for (int t = 0; t < UNR; ++t) acc = mfma_tn(neg4(uj[t]), ui[t], acc);
+  }
+  for (; q < j; ++q) {
+    const d4 uj = load_tileT(L, 16 * j, 16 * q, false);
+    const d4 ui = i == j ? uj : load_tileT(L, 16 * i, 16 * q, false);
+    acc = mfma_tn(neg4(uj), ui, acc);
+  }
+  return acc;
+}
+
+// One workgroup of LW waves per instance.  Block column j of L: wave 0
+// downdates and factors the diagonal block (and advances the forward
+// substitution); then all waves share the off-diagonal blocks of the column:
+// gemm downdate and U(j,i) = V_j^T T(j,i).
+template <int LW>
+__global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
+  constexpr int DU = 2;
+  extern __shared__ double dyn[];
+  __shared__ DiagLds s;
+  __shared__ double vsh[256];
+  __shared__ int sinfo;
+  const int nr = a.nrhs > 0 ? a.nrhs : 1;
+  double *wl = dyn;                          // nbmax * 256
+  double *yl = dyn + (long long)nbmax * 256;  // nbmax * 16 * nr
+  const int t = blockIdx.x;
+  if (t >= a.count) return;
+  const int id = a.ids[t];
+  const int n = a.n[id];
+  const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
+  const int nb = pm;
+  const int w = threadIdx.x >> 6;
+  const int l = lane_id();
+  View A{const_cast<double *>(a.A + a.moff[id]), cn, 0, 0, n, n};
+  View L{a.L + a.moff[id], cn, 0, 0, n, n};
+  double *dAb = L.p + (long long)pm * 16 * cn;
+  const bool has_rhs = a.nrhs > 0;
+  const double *Bb = has_rhs ? a.B + a.voff[id] : nullptr;
+  if (threadIdx.x == 0) sinfo = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const int nv = min(16, n - 16 * j);
+    if (w == 0) {
+      d4 t0 = downdate<DU>(L, j, j, load_tileT(A, 16 * j, 16 * j, true));
+      d4 z = has_rhs ? load_rhs(Bb, ld, n, a.nrhs, j) : zero4();
+      if (has_rhs)
+        for (int q = 0; q < j; ++q)
+          z = mfma_tn(neg4(load_tileT(L, 16 * j, 16 * q, false)),
+                      load_compact(yl + (long long)q * 16 * nr, nr), z);
+      pad_identity(t0, nv);
+      d4 V, W;
+      const int inf = potrf_inv_tile_upper(t0, V, s, &W);
+      if (inf && l == 0 && sinfo == 0) sinfo = 16 * j + inf;
+      store_tileT(L, 16 * j, 16 * j, t0, true);
+      if (l < nv) dAb[16 * j + l] = s.inv[l];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        wl[(long long)j * 256 + 64 * r + l] = W[r];
+        vsh[64 * r + l] = V[r];
+      }
+      if (has_rhs) save_compact(yl + (long long)j * 16 * nr, mfma_tn(V, z, zero4()), nr);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    d4 V;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) V[r] = vsh[64 * r + l];
+    for (int i = j + 1 + w; i < nb; i += LW) {
+      const d4 t1 = downdate<DU>(L, j, i, load_tileT(A, 16 * i, 16 * j, false));
+      store_tileT(L, 16 * i, 16 * j, mfma_tn(V, t1, zero4()), false);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  }
+  if (has_rhs && w == 0) {
+    double *Xb = a.X + a.voff[id];
+    for (int j = nb - 1; j >= 0; --j) {
+      d4 acc = load_compact(yl + (long long)j * 16 * nr, nr);
+      for (int i = j + 1; i < nb; ++i) {
+        const d4 ut = load_tileN(L, 16 * i, 16 * j);  // L(i,j) = U(j,i)^T
+        acc = mfma_tn(neg4(ut), load_compact(yl + (long long)i * 16 * nr, nr), acc);
+      }
+      d4 W;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[r] = wl[(long long)j * 256 + 64 * r + l];
+      const d4 x = mfma_tn(W, acc, zero4());
+      save_compact(yl + (long long)j * 16 * nr, x, nr);
+      store_rhs(Xb, ld, n, a.nrhs, j, x);
+    }
+  }
+  if (a.info && threadIdx.x == 0) a.info[id] = sinfo;
+}
+
+size_t large_lds_bytes(int nbmax, int nrhs) {
+  const int nr = nrhs > 0 ? nrhs : 1;
+  return sizeof(double) * ((size_t)nbmax * 256 + (size_t)nbmax * 16 * nr);
+}
+
+}  // namespace bh
+
+// ---------------------------------------------------------------- plan
+
+using namespace bh;
+
+struct blasfeo_hip_plan {
+  int batch = 0, nrhs = 0;
+  std::vector<int> n;
+  std::vector<long long> moff, voff;  // bytes
+  long long mat_bytes = 0, vec_bytes = 0;
+  int *d_n = nullptr;
+  long long *d_moff = nullptr, *d_voff = nullptr;
+  int *d_ids = nullptr;
+  struct Bucket {
+    int kind;   // 1..4: small kernel with NB = kind; 0: large kernel
+    int first;  // into the id list
+    int count;
+    int nbmax;  // large kernel: blocks of the largest instance
+    int cfg;    // small: waves per block (1, 2, 4); large: waves per instance (4, 8)
+  };
+  std::vector<Bucket> buckets;
+  int use_graph = 1;
+  bool have_graph = false;
+  const void *key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+};
+
+static void drop_graph(blasfeo_hip_plan *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->have_graph = false;
+}
+
+template <int NB>
+static void launch_small(const VbArgs &a, int vw, hipStream_t st) {
+  switch (vw) {
+    case 1: hipLaunchKernelGGL((k_vb_small<NB, 1>), dim3((a.count + 0) / 1), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_vb_small<NB, 2>), dim3((a.count + 1) / 2), dim3(128), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_vb_small<NB, 4>), dim3((a.count + 3) / 4), dim3(256), 0, st, a); break;
+  }
+}
+
+static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Bucket &bk,
+                         const double *A, double *L, const double *B, double *X,
+                         int *info, hipStream_t st) {
+  if (bk.count == 0) return 0;
+  VbArgs a;
+  a.ids = p->d_ids + bk.first;
+  a.count = bk.count;
+  a.n = p->d_n;
+  a.moff = p->d_moff;
+  a.voff = p->d_voff;
+  a.A = A;
+  a.L = L;
+  a.B = B;
+  a.X = X;
+  a.nrhs = p->nrhs;
+  a.info = info;
+  switch (bk.kind) {
+    case 1: launch_small<1>(a, bk.cfg, st); break;
+    case 2: launch_small<2>(a, bk.cfg, st); break;
+    case 3: launch_small<3>(a, bk.cfg, st); break;
+    case 4: launch_small<4>(a, bk.cfg, st); break;
+    default: {
+      const size_t lds = large_lds_bytes(bk.nbmax, p->nrhs);
+      if (bk.cfg == 16)
+        hipLaunchKernelGGL(k_vb_large<16>, dim3(bk.count), dim3(1024), lds, st, a, bk.nbmax);
+      else if (bk.cfg == 8)
+        hipLaunchKernelGGL(k_vb_large<8>, dim3(bk.count), dim3(512), lds, st, a, bk.nbmax);
+      else
+        hipLaunchKernelGGL(k_vb_large<4>, dim3(bk.count), dim3(256), lds, st, a, bk.nbmax);
+    }
+  }
+  return launch_status();
+}
+
+static int launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
+                      const double *B, double *X, int *info, hipStream_t st) {
+  // the large instances first: they are the longest (LPT)
+  for (int pass = 0; pass < 2; ++pass)
+    for (const auto &bk : p->buckets) {
+      if ((pass == 0) != (bk.kind == 0)) continue;
+      int e = launch_bucket(p, bk, A, L, B, X, info, st);
+      if (e) return e;
+    }
+  return 0;
+}
+
+extern "C" {
+
+int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
+                                    blasfeo_hip_plan **plan) {
+  if (batch < 0) return -1;
+  if (batch > 0 && !n_host) return -2;
+  if (nrhs < 0 || nrhs > 16) return -3;
+  if (!plan) return -4;
+  for (int i = 0; i < batch; ++i)
+    if (n_host[i] < 1 || n_host[i] > 512) return -2;
+  auto *p = new blasfeo_hip_plan();
+  p->batch = batch;
+  p->nrhs = nrhs;
+  p->n.assign(n_host, n_host + batch);
+  p->moff.resize(batch);
+  p->voff.resize(batch);
+  long long mo = 0, vo = 0;
+  for (int i = 0; i < batch; ++i) {
+    p->moff[i] = mo;
+    p->voff[i] = vo;
+    mo += blasfeo_memsize_dmat(p->n[i], p->n[i]);
+    vo += ((long long)(p->n[i] + 15) / 16 * 16 * (nrhs > 0 ? nrhs : 1) * 8 + 255) / 256 * 256;
+  }
+  p->mat_bytes = mo;
+  p->vec_bytes = vo;
+  // buckets: small kernels by number of 16-blocks, one large bucket
+  std::vector<int> ids;
+  ids.reserve(batch);
+  for (int kind = 1; kind <= 4; ++kind) {
+    const int first = (int)ids.size();
+    for (int i = 0; i < batch; ++i)
+      if ((p->n[i] + 15) / 16 == kind) ids.push_back(i);
+    p->buckets.push_back({kind, first, (int)ids.size() - first, kind, 2});
+  }
+  {
+    const int first = (int)ids.size();
+    std::vector<int> big;
+    for (int i = 0; i < batch; ++i)
+      if (p->n[i] > 64) big.push_back(i);
+    std::stable_sort(big.begin(), big.end(),
+                     [&](int x, int y) { return p->n[x] > p->n[y]; });
+    ids.insert(ids.end(), big.begin(), big.end());
+    const int nbmax = big.empty() ? 0 : (p->n[big[0]] + 15) / 16;
+    p->buckets.push_back({0, first, (int)big.size(), nbmax, 4});
+  }
+  std::vector<long long> md(batch), vd(batch);
+  for (int i = 0; i < batch; ++i) {
+    md[i] = p->moff[i] / 8;
+    vd[i] = p->voff[i] / 8;
+  }
+  hipError_t e = hipSuccess;
+  const size_t nb = (size_t)(batch > 0 ? batch : 1);
+  if (e == hipSuccess) e = hipMalloc(&p->d_n, nb * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&p->d_moff, nb * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&p->d_voff, nb * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&p->d_ids, nb * sizeof(int));
+  if (e == hipSuccess && batch > 0) {
+    e = hipMemcpy(p->d_n, p->n.data(), batch * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_moff, md.data(), batch * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_voff, vd.data(), batch * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_ids, ids.data(), batch * sizeof(int), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && p->buckets.back().count > 0) {
+    // the large kernel's dynamic LDS may exceed the default limit
+    const int lds = (int)large_lds_bytes(p->buckets.back().nbmax, nrhs);
+    e = hipFuncSetAttribute((const void *)k_vb_large<8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_vb_large<16>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_vb_large<4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  }
+  if (e != hipSuccess) {
+    blasfeo_hip_plan_destroy(p);
+    return (int)e;
+  }
+  *plan = p;
+  return 0;
+}
+
+int blasfeo_hip_plan_layout(const blasfeo_hip_plan *p, long long *mat_off,
+                            long long *vec_off, long long *mat_bytes,
+                            long long *vec_bytes) {
+  if (!p) return -1;
+  if (mat_off) std::copy(p->moff.begin(), p->moff.end(), mat_off);
+  if (vec_off) std::copy(p->voff.begin(), p->voff.end(), vec_off);
+  if (mat_bytes) *mat_bytes = p->mat_bytes;
+  if (vec_bytes) *vec_bytes = p->vec_bytes;
+  return 0;
+}
+
+int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *p, int on) {
+  if (!p) return -1;
+  p->use_graph = on ? 1 : 0;
+  drop_graph(p);
+  return 0;
+}
+
+int blasfeo_hip_plan_config(const blasfeo_hip_plan *p, int *cfg_out) {
+  if (!p) return -1;
+  if (cfg_out)
+    for (size_t i = 0; i < p->buckets.size(); ++i) cfg_out[i] = p->buckets[i].cfg;
+  return (int)p->buckets.size();
+}
+
+int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *p, const void *A, void *L,
+                               const void *B, void *X, int *info,
+                               void *stream) {
+  if (!p) return -1;
+  if (p->batch == 0) return 0;
+  if (!A) return -2;
+  if (!L) return -3;
+  if (p->nrhs > 0 && !B) return -4;
+  if (p->nrhs > 0 && !X) return -5;
+  hipStream_t st = (hipStream_t)stream;
+  const double *Ad = (const double *)A;
+  double *Ld = (double *)L;
+  const double *Bd = (const double *)B;
+  double *Xd = (double *)X;
+  if (!p->use_graph) return launch_all(p, Ad, Ld, Bd, Xd, info, st);
+  const void *key[5] = {A, L, B, X, info};
+  bool same = p->have_graph;
+  for (int i = 0; i < 5 && same; ++i) same = key[i] == p->key[i];
+  if (!same) {
+    drop_graph(p);
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return (int)e;
+    int le = launch_all(p, Ad, Ld, Bd, Xd, info, p->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap, &g);
+    if (le) {
+      if (g) (void)hipGraphDestroy(g);
+      return le;
+    }
+    if (e != hipSuccess) return (int)e;
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return (int)e;
+    }
+    p->graph = g;
+    p->have_graph = true;
+    for (int i = 0; i < 5; ++i) p->key[i] = key[i];
+  }
+  hipError_t e = hipGraphLaunch(p->exec, st);
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
+                              const void *B, void *X, int *info, void *stream) {
+  if (!p) return -1;
+  if (p->batch == 0) return 0;
+  if (!A || !L || (p->nrhs > 0 && (!B || !X))) return -2;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -3;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -3;
+  }
+  int err = 0;
+  for (auto &bk : p->buckets) {
+    if (bk.count == 0) continue;
+    const int cands_small[3] = {1, 2, 4};
+    const int cands_large[3] = {4, 8, 16};
+    const int *cands = bk.kind ? cands_small : cands_large;
+    const int nc = 3;
+    float best = 1e30f;
+    int best_cfg = bk.cfg;
+    for (int ci = 0; ci < nc && !err; ++ci) {
+      bk.cfg = cands[ci];
+      float tot = 0.f;
+      for (int rep = 0; rep < 3 && !err; ++rep) {
+        (void)hipEventRecord(e0, st);
+        err = launch_bucket(p, bk, (const double *)A, (double *)L,
+                            (const double *)B, (double *)X, info, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;  // first run warms up
+      }
+      if (tot < best) {
+        best = tot;
+        best_cfg = cands[ci];
+      }
+    }
+    bk.cfg = best_cfg;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(p);
+  return err;
+}
+
+void blasfeo_hip_plan_destroy(blasfeo_hip_plan *p) {
+  if (!p) return;
+  drop_graph(p);
+  if (p->d_n) (void)hipFree(p->d_n);
+  if (p->d_moff) (void)hipFree(p->d_moff);
+  if (p->d_voff) (void)hipFree(p->d_voff);
+  if (p->d_ids) (void)hipFree(p->d_ids);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+"""GPU parity of the uneven-batch plan (potrf_l + forward/back substitution,
+size-bucketed kernels, captured hipGraph) against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import assert_parity, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1704_02457_amd as p  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+SIZES = [1, 5, 8, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64, 65, 80, 100, 127, 128, 129, 200, 256, 300]
+
+
+def build(ns, nrhs, seed=3):
+    rng = np.random.default_rng(seed)
+    mats, rhs = [], []
+    for n in ns:
+        G = rng.standard_normal((n, n))
+        A = G @ G.T + n * np.eye(n)
+        mats.append(0.5 * (A + A.T))
+        rhs.append(rng.standard_normal((n, max(nrhs, 1)))[:, :nrhs])
+    plan = p.VbPlan(ns, nrhs)
+    A = plan.mat_arena(fill=np.nan)
+    L = plan.mat_arena(fill=np.nan)
+    B = plan.vec_arena()
+    X = plan.vec_arena(fill=np.nan)
+    for i, n in enumerate(ns):
+        # only the lower triangle of A may be read
+        Ai = np.tril(mats[i]) + np.triu(np.full((n, n), np.nan), 1)
+        p.pack(torch.as_tensor(Ai, device=DEV), out=plan.dmat(A, i))
+        if nrhs:
+            plan.rhs(B, i).copy_(torch.as_tensor(rhs[i], device=DEV))
+    info = torch.full((len(ns),), -5, dtype=torch.int32, device=DEV)
+    return plan, mats, rhs, A, L, B, X, info
+
+
+def check_all(plan, mats, rhs, L, X, info, nrhs, what):
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    for i, n in enumerate(plan.ns):
+        n = int(n)
+        Lr, dAr, ir = oracle.dpotrf_l(mats[i])
+        assert ir == 0 and inf[i] == 0, (what, i, inf[i])
+        Lg = p.unpack(plan.dmat(L, i)).cpu().numpy()
+        assert_parity(np.tril(Lg), Lr, n, f"{what} L n={n}")
+        assert np.all(np.isnan(Lg[np.triu_indices(n, 1)])), f"{what}: upper part written (n={n})"
+        assert_parity(plan.dmat(L, i).dA()[:n].cpu().numpy(), dAr, n, f"{what} dA n={n}")
+        if nrhs:
+            Xr = oracle.dpotrs_l(Lr, rhs[i])
+            Xg = plan.rhs(X, i).cpu().numpy()
+            assert_parity(Xg, Xr, n, f"{what} X n={n}")
+
+
+@pytest.mark.parametrize("nrhs", [1, 4, 0])
+def test_vbatched_mixed_sizes(nrhs):
+    note("vbatched", nrhs)
+    plan, mats, rhs, A, L, B, X, info = build(SIZES, nrhs)
+    plan.set_graph(False)
+    plan.solve(A, L, B, X, info)
+    check_all(plan, mats, rhs, L, X, info, nrhs, "eager")
+
+
+def test_vbatched_graph_replay_and_autotune():
+    note("vbatched graph")
+    ns = [7, 16, 40, 64, 70, 130, 33, 90]
+    plan, mats, rhs, A, L, B, X, info = build(ns, 2, seed=8)
+    plan.solve(A, L, B, X, info)  # captures the graph
+    check_all(plan, mats, rhs, L, X, info, 2, "graph first")
+    X0 = X.clone()
+    for rep in range(3):  # replays, with eager work and syncs in between
+        X.fill_(np.nan)
+        L.fill_(np.nan)
+        torch.cuda.synchronize()
+        plan.solve(A, L, B, X, info)
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(X, nan=123.0), torch.nan_to_num(X0, nan=123.0)), rep
+    # new data through the same pointers: the replayed graph must see it
+    rng = np.random.default_rng(99)
+    for i, n in enumerate(ns):
+        G = rng.standard_normal((n, n))
+        mats[i] = G @ G.T + n * np.eye(n)
+        p.pack(torch.as_tensor(mats[i], device=DEV), out=plan.dmat(A, i))
+    plan.solve(A, L, B, X, info)
+    check_all(plan, mats, rhs, L, X, info, 2, "graph new data")
+    plan.autotune(A, L, B, X, info)
+    assert len(plan.config()) == 5
+    plan.solve(A, L, B, X, info)
+    check_all(plan, mats, rhs, L, X, info, 2, "after autotune")
+
+
+def test_vbatched_failure_is_per_instance():
+    note("vbatched failure")
+    ns = [20, 64, 100, 48, 150]
+    plan, mats, rhs, A, L, B, X, info = build(ns, 1, seed=4)
+    bad = {1: 37, 2: 70, 4: 0}
+    for i, col in bad.items():
+        M = mats[i].copy()
+        M[col, col] = -1.0
+        mats[i] = M
+        p.pack(torch.as_tensor(M, device=DEV), out=plan.dmat(A, i))
+    plan.solve(A, L, B, X, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    for i, n in enumerate(ns):
+        Lr, _, ir = oracle.dpotrf_l(mats[i])
+        assert inf[i] == ir, (i, inf[i], ir)
+        if ir == 0:
+            Lg = p.unpack(plan.dmat(L, i)).cpu().numpy()
+            assert_parity(np.tril(Lg), Lr, n, f"L {i}")
+            assert_parity(plan.rhs(X, i).cpu().numpy(), oracle.dpotrs_l(Lr, rhs[i]), n, f"X {i}")
+    assert [inf[i] for i in bad] == [col + 1 for col in bad.values()]
+
+
+def test_vbatched_full_size_sampled():
+    """The uneven workload at full size (65536 systems, n = 8*U{1..32}, one
+    right-hand side) in the benchmark's configuration; 64 sampled systems
+    are compared element by element with the oracle, and every system is
+    checked through its info code and residual."""
+    note("vbatched full size")
+    batch = 65536
+    ns = synth.uneven_sizes(batch, seed=2)
+    plan = p.VbPlan(ns, 1)
+    A = plan.mat_arena()
+    L = plan.mat_arena(fill=0.0)
+    B = plan.vec_arena()
+    X = plan.vec_arena()
+    classes = synth.uneven_batch_device(ns, seed=2)
+    for n, (idx, An, bn) in classes.items():
+        plan.pack_class(n, idx, An, A)
+    for n, (idx, An, bn) in classes.items():
+        plan.scatter_rhs(n, idx, bn, B)
+    info = torch.full((batch,), -5, dtype=torch.int32, device=DEV)
+    plan.solve(A, L, B, X, info)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum().item()) == 0
+    rng = np.random.default_rng(1)
+    sample = []
+    for n, (idx, An, bn) in classes.items():
+        sample += [(n, int(idx[t]), t) for t in range(min(2, len(idx)))]
+    for n, i, t in sample:
+        Ah = classes[n][1][t].cpu().numpy()
+        Lr, dAr, ir = oracle.dpotrf_l(Ah)
+        Lg = np.tril(p.unpack(plan.dmat(L, i)).cpu().numpy())
+        assert_parity(Lg, Lr, n, f"L n={n} i={i}")
+        bh = plan.rhs(B, i).cpu().numpy()
+        assert_parity(plan.rhs(X, i).cpu().numpy(), oracle.dpotrs_l(Lr, bh), n, f"x n={n} i={i}")
+    # residual of every instance of one size class, computed on the GPU
+    n = 256
+    idx, An, bn = classes[n]
+    Lall = torch.stack([p.unpack(plan.dmat(L, int(i))) for i in idx[:64]])
+    Lall = torch.tril(Lall)
+    R = torch.bmm(Lall, Lall.transpose(1, 2).contiguous()) - An[:64]
+    assert float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(An[:64])).max()) < 256 * 1e-15
+    del rng
