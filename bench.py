@@ -109,6 +109,35 @@ def bench_uneven(p, synth, torch, batch=65536, reps=5):
     return out
 
 
+def riccati_stage_flops(nx, nu):
+    """Per stage: trmm C = X Lc (X (nu+nx)-by-nx, Lc lower), syrk C C^T,
+    potrf of order nu+nx (LAPACK Working Note 41 counts)."""
+    nm = nx + nu
+    return nm * nx * nx + nm * (nm + 1) * nx + flops_potrf(nm)
+
+
+def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
+    """The Riccati workload: 4096 backward recursions, nx=32, nu=8, N=20."""
+    d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
+    dev = torch.device("cuda:0")
+    sA, sB = p.pack_batch(torch.as_tensor(d["A"], device=dev)), p.pack_batch(torch.as_tensor(d["B"], device=dev))
+    sQ, sR = p.pack_batch(torch.as_tensor(d["Q"], device=dev)), p.pack_batch(torch.as_tensor(d["R"], device=dev))
+    sP = p.pack_batch(torch.as_tensor(d["PN"], device=dev))
+    sF = p.DMatBatch(batch * N, nx + nu, nx + nu, fill=0.0)
+    info = torch.zeros(batch, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    _, per = time_events(lambda: p.blasfeo_hip_dric_trf_batched(batch, nx, nu, N, sA, sB, sQ, sR, sP, sF, info,
+                                                                stream), reps, 2, stream)
+    ms = float(np.median(per))
+    fl = batch * N * riccati_stage_flops(nx, nu)
+    out = {"riccati_ms": round(ms, 3), "riccati_gflops": round(fl / ms / 1e6, 1),
+           "riccati_recursions_per_s": round(batch / ms * 1e3, 1),
+           "riccati_failed": int((info != 0).sum().item())}
+    del sF
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_events(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -217,6 +246,8 @@ def main():
     if not args.no_extra:
         print("[bench] uneven batch (65536 solves)", file=sys.stderr, flush=True)
         extra.update(bench_uneven(p, synth, torch))
+        print("[bench] Riccati batch (4096 x N=20)", file=sys.stderr, flush=True)
+        extra.update(bench_riccati(p, synth, torch))
 
     if args.calib_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

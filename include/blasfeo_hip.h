@@ -265,6 +265,26 @@ int blasfeo_hip_dsyrk_dpotrf_trsm_batched(int batch, int m, int k, int nrhs,
                                           const struct blasfeo_dmat *sX,
                                           int *info, void *stream);
 
+/* Backward Riccati recursion in square-root form (§5.3), one problem per
+ * instance, all N stages in one kernel with no host round trip:
+ *   C = [B^T; A^T] Lc_{n+1},  M = blockdiag(R, Q) + C C^T,
+ *   F_n = chol(M) = [[Lambda_n, 0], [L_n, Lc_n]],  Lc_N = chol(P_N),
+ * for n = N-1 down to 0, with x+ = A x + B u and S = 0 (the reading of the
+ * section's equations adopted by this library).  Inputs per instance (uniform
+ * batches, lower triangles of Q, R, P_N read): A nx-by-nx, B nx-by-nu, Q, R,
+ * P_N.  Output: F is a uniform batch of batch*N matrices of order nu+nx;
+ * chunk b*N + n receives the lower triangle of F_n of problem b.  info[b] =
+ * 0, or 1000*(n+1) + j for the first failing pivot j (1-based, unpadded)
+ * of stage n (n = N for chol(P_N)).  Limits: 1 <= nx <= 32, 1 <= nu <= 16. */
+int blasfeo_hip_dric_trf_batched(int batch, int nx, int nu, int N,
+                                 const struct blasfeo_dmat *sA,
+                                 const struct blasfeo_dmat *sB,
+                                 const struct blasfeo_dmat *sQ,
+                                 const struct blasfeo_dmat *sR,
+                                 const struct blasfeo_dmat *sP,
+                                 const struct blasfeo_dmat *sF, int *info,
+                                 void *stream);
+
 /* ------------------------------------------------------------------------
  * Uneven batches: plans.  A plan is created once for a list of orders and
  * executed many times (the embedded-optimization pattern of §2: the same

@@ -1,0 +1,243 @@
+// Backward Riccati recursion in square-root form (§5.3), a batch of
+// independent problems, one wavefront per problem, all N stages with the
+// stage matrices register resident (no host round trip between stages).
+//
+// With dynamics x+ = A x + B u (A nx-by-nx, B nx-by-nu), cost blocks Q, R
+// (S = 0) and terminal P_N, for n = N-1 down to 0:
+//   C   = [B^T; A^T] Lc_{n+1}                 (Lc lower, nx-by-nx)
+//   M   = blockdiag(R, Q) + C C^T
+//   F_n = chol(M) = [[Lambda_n, 0], [L_n, Lc_n]],   Lc_N = chol(P_N).
+// The control block is padded from nu to a whole number of 16-row blocks
+// with an identity block, so Lc_n always starts on a block boundary of the
+// padded factor and no realignment is needed between stages; the padding is
+// dropped when F_n is stored.  In the T-tile view (blocks.hpp):
+//   Ct(k,j)  = sum_m Ln(m,k)^T X^T(m,j)        (Ct = C^T, X = [B^T; 0; A^T])
+//   T(j,i)   = RQ(j,i) + sum_k Ct(k,j)^T Ct(k,i)
+// then the register factorization of T, and Ln(m,k) = U(k+nub, m+nub)^T
+// for the next stage (one LDS transpose per block).
+#include "common.hpp"
+
+namespace bh {
+
+struct RicArgs {
+  int batch, nx, nu, N;
+  View A, B, Q, R, P;  // instance 0; offsets are per-instance strides below
+  long long sA, sB, sQ, sR, sP;
+  double *F;  // stage factors, chunk (b*N + n) at F + (b*N + n)*sF
+  int cnF;
+  long long sF;
+  int *info;
+};
+
+// padded index (u block padded to 16*NUB rows) -> unpadded index, or -1
+template <int NUB>
+__device__ __forceinline__ int unpad(int x, int nu) {
+  if (x < nu) return x;
+  if (x < 16 * NUB) return -1;
+  return x - 16 * NUB + nu;
+}
+
+template <int NUB, int NXB>
+__global__ __launch_bounds__(64) void k_ric_trf(RicArgs a) {
+  constexpr int NB = NUB + NXB;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int NLT = NXB * (NXB + 1) / 2;
+  __shared__ DiagLds s;
+  const long long b = blockIdx.x;
+  if (b >= a.batch) return;
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int nu = a.nu, nx = a.nx;
+  View A = a.A, B = a.B, Q = a.Q, R = a.R, P = a.P;
+  A.p += b * a.sA;
+  B.p += b * a.sB;
+  Q.p += b * a.sQ;
+  R.p += b * a.sR;
+  P.p += b * a.sP;
+
+  // X^T tiles: logical X^T(m, j) block, X = [B^T; 0; A^T] (padded rows)
+  d4 Xt[NXB][NB];
+#pragma unroll
+  for (int m = 0; m < NXB; ++m) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < NUB) {
+        // X(16j + q, 16m + p) = B(16m + p, 16j + q) for 16j + q < nu
+        Xt[m][j] = load_tileN(B, 16 * m, 16 * j);
+      } else {
+        Xt[m][j] = load_tileN(A, 16 * m, 16 * (j - NUB));
+      }
+    }
+  }
+
+  // Lc_N = chol(P_N): register factorization of the NXB x NXB block
+  d4 Ln[NLT];  // Ln(m,k), m >= k, logical Lc(m,k), index tix_up(k, m)
+  int info = 0;
+  {
+    d4 T[NLT];
+#pragma unroll
+    for (int i = 0; i < NXB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) T[tix_up(j, i)] = load_tileT(P, 16 * i, 16 * j, i == j);
+#pragma unroll
+    for (int j = 0; j < NXB; ++j) {
+      d4 &D = T[tix_up(j, j)];
+      const int nv = min(16, nx - 16 * j);
+      if (nv < 16) pad_identity(D, nv);
+      d4 V;
+      const int inf = potrf_inv_tile_upper(D, V, s);
+      if (inf && info == 0) info = 1000 * (a.N + 1) + 16 * j + inf;
+#pragma unroll
+      for (int i = j + 1; i < NXB; ++i) T[tix_up(j, i)] = mfma_tn(V, T[tix_up(j, i)], zero4());
+#pragma unroll
+      for (int q = j + 1; q < NXB; ++q) {
+        const d4 nu4 = neg4(T[tix_up(j, q)]);
+#pragma unroll
+        for (int i = q; i < NXB; ++i)
+          T[tix_up(q, i)] = mfma_tn(nu4, T[tix_up(j, i)], T[tix_up(q, i)]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NXB; ++m)
+#pragma unroll
+      for (int k = 0; k <= m; ++k) Ln[tix_up(k, m)] = transpose_tile(T[tix_up(k, m)], s.tr);
+  }
+
+  for (int n = a.N - 1; n >= 0; --n) {
+    // Ct(k, j) = sum_{m >= k} Ln(m,k)^T X^T(m,j)
+    d4 T[NT];
+    {
+      d4 Ct[NXB][NB];
+#pragma unroll
+      for (int k = 0; k < NXB; ++k)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          d4 acc = zero4();
+#pragma unroll
+          for (int m = k; m < NXB; ++m) acc = mfma_tn(Ln[tix_up(k, m)], Xt[m][j], acc);
+          Ct[k][j] = acc;
+        }
+      // T(j,i) = blockdiag(R, I, Q)(j,i) + sum_k Ct(k,j)^T Ct(k,i)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+          d4 acc;
+          if (i < NUB) {
+            acc = load_tileT(R, 16 * i, 16 * j, i == j);
+            if (i == j) {  // identity on the padding rows nu..16*NUB-1
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int p = 16 * j + g + 4 * r, q = 16 * i + c;
+                if (p >= nu || q >= nu) acc[r] = (p == q) ? 1.0 : 0.0;
+              }
+            }
+          } else if (j < NUB) {
+            acc = zero4();
+          } else {
+            acc = load_tileT(Q, 16 * (i - NUB), 16 * (j - NUB), i == j);
+            if (i == j) {
+              const int nv = min(16, nx - 16 * (j - NUB));
+              if (nv < 16) pad_identity(acc, nv);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < NXB; ++k) acc = mfma_tn(Ct[k][j], Ct[k][i], acc);
+          T[tix_up(j, i)] = acc;
+        }
+    }
+    // F_n = chol(M): register factorization, stored without the padding
+    double *Fb = a.F + (b * a.N + n) * a.sF;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      d4 &D = T[tix_up(j, j)];
+      d4 V;
+      const int inf = potrf_inv_tile_upper(D, V, s);
+      if (inf && info == 0) {
+        // report the pivot as an index of the unpadded stage matrix
+        const int pv = unpad<NUB>(16 * j + inf - 1, nu);
+        info = 1000 * (n + 1) + (pv >= 0 ? pv + 1 : 16 * j + inf);
+      }
+#pragma unroll
+      for (int i = j + 1; i < NB; ++i) T[tix_up(j, i)] = mfma_tn(V, T[tix_up(j, i)], zero4());
+#pragma unroll
+      for (int q = j + 1; q < NB; ++q) {
+        const d4 nu4 = neg4(T[tix_up(j, q)]);
+#pragma unroll
+        for (int i = q; i < NB; ++i)
+          T[tix_up(q, i)] = mfma_tn(nu4, T[tix_up(j, i)], T[tix_up(q, i)]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        const d4 &t = T[tix_up(j, i)];  // U(j,i) = F(i,j)^T
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ro = unpad<NUB>(16 * i + c, nu), co = unpad<NUB>(16 * j + g + 4 * r, nu);
+          if (ro >= 0 && co >= 0 && ro < nu + nx && co < nu + nx && ro >= co)
+            Fb[pm_off(ro, co, a.cnF)] = t[r];
+        }
+      }
+    // Lc_n = trailing NXB x NXB blocks of the padded factor
+#pragma unroll
+    for (int m = 0; m < NXB; ++m)
+#pragma unroll
+      for (int k = 0; k <= m; ++k)
+        Ln[tix_up(k, m)] = transpose_tile(T[tix_up(k + NUB, m + NUB)], s.tr);
+  }
+  if (a.info && l == 0) a.info[b] = info;
+}
+
+template <int NUB, int NXB>
+static void launch_ric(const RicArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_ric_trf<NUB, NXB>), dim3(a.batch), dim3(64), 0, st, a);
+}
+
+}  // namespace bh
+
+using namespace bh;
+
+extern "C" int blasfeo_hip_dric_trf_batched(
+    int batch, int nx, int nu, int N, const struct blasfeo_dmat *sA,
+    const struct blasfeo_dmat *sB, const struct blasfeo_dmat *sQ,
+    const struct blasfeo_dmat *sR, const struct blasfeo_dmat *sP,
+    const struct blasfeo_dmat *sF, int *info, void *stream) {
+  if (batch < 0) return -1;
+  if (nx < 1 || nx > 32) return -2;
+  if (nu < 1 || nu > 16) return -3;
+  if (N < 1) return -4;
+  if (!operand_ok(sA, 0, 0, nx, nx)) return -5;
+  if (!operand_ok(sB, 0, 0, nx, nu)) return -6;
+  if (!operand_ok(sQ, 0, 0, nx, nx)) return -7;
+  if (!operand_ok(sR, 0, 0, nu, nu)) return -8;
+  if (!operand_ok(sP, 0, 0, nx, nx)) return -9;
+  if (!operand_ok(sF, 0, 0, nu + nx, nu + nx)) return -10;
+  if (batch == 0) return 0;
+  RicArgs a;
+  a.batch = batch;
+  a.nx = nx;
+  a.nu = nu;
+  a.N = N;
+  a.A = make_view(sA, 0, 0, nx, nx);
+  a.B = make_view(sB, 0, 0, nx, nu);
+  a.Q = make_view(sQ, 0, 0, nx, nx);
+  a.R = make_view(sR, 0, 0, nu, nu);
+  a.P = make_view(sP, 0, 0, nx, nx);
+  a.sA = batch_stride(sA);
+  a.sB = batch_stride(sB);
+  a.sQ = batch_stride(sQ);
+  a.sR = batch_stride(sR);
+  a.sP = batch_stride(sP);
+  a.F = sF->pA;
+  a.cnF = sF->cn;
+  a.sF = batch_stride(sF);
+  a.info = info;
+  hipStream_t st = (hipStream_t)stream;
+  if (nx <= 16)
+    launch_ric<1, 1>(a, st);
+  else
+    launch_ric<1, 2>(a, st);
+  return launch_status();
+}

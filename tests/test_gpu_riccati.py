@@ -1,0 +1,118 @@
+"""GPU parity of the batched backward Riccati recursion (square-root form)
+against the CPU oracle (which is itself pinned against the classical Riccati
+difference equation and hand-derived cases)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import assert_parity, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1704_02457_amd as p  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def run(d, N, poison=True):
+    batch, nx, nu = d["B"].shape
+    nm = nx + nu
+    sA, sB = p.pack_batch(dev(d["A"])), p.pack_batch(dev(d["B"]))
+    # only the lower triangles of Q, R, P_N may be read
+    def low(X):
+        X = np.array(X, dtype=float)
+        iu = np.triu_indices(X.shape[1], 1)
+        X[:, iu[0], iu[1]] = np.nan
+        return X
+    sQ, sR, sP = p.pack_batch(dev(low(d["Q"]))), p.pack_batch(dev(low(d["R"]))), p.pack_batch(dev(low(d["PN"])))
+    sF = p.DMatBatch(batch * N, nm, nm, fill=np.nan if poison else 0.0)
+    info = torch.full((batch,), -9, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dric_trf_batched(batch, nx, nu, N, sA, sB, sQ, sR, sP, sF, info)
+    torch.cuda.synchronize()
+    F = p.unpack_batch(sF).cpu().numpy().reshape(batch, N, nm, nm)
+    return F, info.cpu().numpy()
+
+
+@pytest.mark.parametrize("nx,nu,N", [(32, 8, 20), (32, 8, 1), (20, 3, 5), (16, 16, 4), (5, 2, 7), (32, 16, 3), (1, 1, 6)])
+def test_riccati_parity(nx, nu, N):
+    note("riccati", nx, nu, N)
+    batch = 9
+    d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
+    # a non-trivial SPD R and Q for some instances
+    rng = np.random.default_rng(nx * 7 + nu)
+    for b in range(0, batch, 2):
+        G = rng.standard_normal((nu, nu))
+        d["R"][b] = G @ G.T / nu + 0.1 * np.eye(nu)
+        H = rng.standard_normal((nx, nx))
+        d["Q"][b] = H @ H.T / nx + np.eye(nx)
+    F, info = run(d, N)
+    Fr, infr, _ = oracle.batch_ric_trf(d["A"], d["B"], d["Q"], d["R"], d["PN"], N, nthreads=4)
+    assert np.all(infr == 0) and np.all(info == 0), info
+    for b in range(batch):
+        for n in range(N):
+            assert_parity(np.tril(F[b, n]), Fr[b, n], nx + nu, f"F b={b} n={n}")
+            assert np.all(np.isnan(F[b, n][np.triu_indices(nx + nu, 1)]))
+
+
+def test_riccati_closed_form():
+    """B = 0, A = I, Q = I, P_N = I: Lc_n = sqrt(N - n + 1) I, Lambda_n = chol(R)."""
+    note("riccati closed form")
+    nx, nu, N, batch = 32, 8, 20, 3
+    d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
+    d["A"][:] = np.eye(nx)
+    d["B"][:] = 0.0
+    d["R"][:] = np.diag(np.arange(1, nu + 1, dtype=float) ** 2)
+    F, info = run(d, N, poison=False)
+    assert np.all(info == 0)
+    for n in range(N):
+        Lc = F[:, n, nu:, nu:]
+        assert np.allclose(Lc, np.sqrt(N - n + 1.0) * np.eye(nx), rtol=1e-14, atol=0)
+        assert np.array_equal(F[:, n, :nu, :nu], np.broadcast_to(np.diag(np.arange(1, nu + 1.0)), (batch, nu, nu)))
+        assert np.count_nonzero(F[:, n, nu:, :nu]) == 0
+
+
+def test_riccati_failure_is_per_instance():
+    note("riccati failure")
+    nx, nu, N, batch = 32, 8, 6, 4
+    d = synth.riccati_batch(batch, seed=5, nx=nx, nu=nu)
+    d["R"][1] = -100.0 * np.eye(nu)   # stage N-1 fails at pivot 1
+    d["PN"][2][5, 5] = -1.0           # chol(P_N) fails at pivot 6
+    F, info = run(d, N, poison=False)
+    Fr, infr, _ = oracle.batch_ric_trf(d["A"], d["B"], d["Q"], d["R"], d["PN"], N, nthreads=2)
+    assert list(info) == list(infr), (info, infr)
+    assert infr[1] == 1000 * N + 1 and infr[2] == 1000 * (N + 1) + 6
+    for b in (0, 3):
+        for n in range(N):
+            assert_parity(np.tril(F[b, n]), Fr[b, n], nx + nu, f"F b={b} n={n}")
+
+
+def test_riccati_full_size_sampled():
+    """The full Riccati workload (4096 problems, nx = 32, nu = 8, N = 20) in
+    the benchmark's launch configuration; 16 sampled problems element by
+    element against the oracle, every problem through its info code and the
+    identity F_n F_n^T = M_n of its last stage factor's leading block."""
+    note("riccati full size")
+    batch, nx, nu, N = 4096, 32, 8, 20
+    d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
+    F, info = run(d, N, poison=False)
+    assert np.all(info == 0)
+    idx = np.random.default_rng(0).choice(batch, 16, replace=False)
+    sub = {k: v[idx] for k, v in d.items()}
+    Fr, infr, _ = oracle.batch_ric_trf(sub["A"], sub["B"], sub["Q"], sub["R"], sub["PN"], N, nthreads=8)
+    for t, b in enumerate(idx):
+        for n in (0, N // 2, N - 1):
+            assert_parity(np.tril(F[b, n]), Fr[t, n], nx + nu, f"F b={b} n={n}")
+    # every problem: the stage-(N-1) factor reproduces R + B^T B (P_N = I)
+    Lam = np.tril(F[:, N - 1, :nu, :nu])
+    M = d["R"] + np.einsum("bki,bkj->bij", d["B"], d["B"])
+    res = np.linalg.norm(Lam @ np.swapaxes(Lam, 1, 2) - M, axis=(1, 2)) / np.linalg.norm(M, axis=(1, 2))
+    assert res.max() < 1e-14
