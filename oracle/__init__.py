@@ -49,8 +49,15 @@ def lib():
         L.orc_spotrf_l.argtypes = [_i, _fp, _i, _fp, _i]
         L.orc_spotrf_l.restype = _i
         L.orc_spotrs_l.argtypes = [_i, _fp, _i, _fp, _fp]
-        L.orc_dposv_mixed.argtypes = [_i, _dp, _i, _dp, _d, _i, _dp, _dp]
+        L.orc_dposv_mixed.argtypes = [_i, _dp, _i, _dp, _d, _i, _i, _dp, _dp]
         L.orc_dposv_mixed.restype = _i
+        L.orc_fl16.argtypes = [ctypes.c_float]
+        L.orc_fl16.restype = ctypes.c_float
+        L.orc_mixed_scale.argtypes = [_i, _dp, _i, _dp]
+        L.orc_mixed_factor.argtypes = [_i, _dp, _i, _i, _fp, _i, _dp]
+        L.orc_mixed_factor.restype = _i
+        L.orc_batch_dposv_mixed.argtypes = [_i, _ip, _lp, _lp, _dp, _dp, _i, _d, _i, _i, _dp, _ip, _dp, _i]
+        L.orc_batch_dposv_mixed.restype = _i
         L.orc_batch_syrk_potrf_trsm.argtypes = [_i, _i, _i, _i, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _i]
         L.orc_batch_syrk_potrf_trsm.restype = _i
         L.orc_batch_potrf_potrs.argtypes = [_i, _ip, _lp, _lp, _dp, _dp, _dp, _dp, _dp, _ip, _i]
@@ -171,14 +178,42 @@ def spotrf_l(C):
     return D, info
 
 
-def dposv_mixed(A, b, tol=1e-12, max_iter=10):
-    """(x, iterations or negative code, eta) of the FP32-factor + FP64-refinement solve."""
+FP32, FP16_SCALED = 1, 2
+
+
+def fl16(x):
+    """Nearest binary16 value of the binary32 value x, as a Python float."""
+    return float(lib().orc_fl16(float(np.float32(x))))
+
+
+def mixed_scale(A):
+    """Power-of-two diagonal scaling s of the mixed-precision solve."""
+    A = _f64(A)
+    n = A.shape[0]
+    s = np.zeros(n)
+    lib().orc_mixed_scale(n, _p(A), _ld(A), _p(s))
+    return s
+
+
+def mixed_factor(A, prec=FP32):
+    """(L32, s, info): low-precision Cholesky factor of S A S, S = diag(s)."""
+    A = _f64(A)
+    n = A.shape[0]
+    L = np.zeros((n, n), dtype=np.float32, order="F")
+    s = np.zeros(n)
+    info = lib().orc_mixed_factor(n, _p(A), _ld(A), prec, L.ctypes.data_as(_fp), max(1, n), _p(s))
+    return L, s, info
+
+
+def dposv_mixed(A, b, tol=1e-12, max_iter=10, prec=FP32):
+    """(x, corrections or negative code, eta) of the low-precision-factor +
+    FP64-refinement solve (-1: factorization failed, -2: gave up)."""
     A = _f64(A)
     b = _f64(b).ravel()
     n = A.shape[0]
     x = np.zeros(n)
     eta = np.zeros(1)
-    it = lib().orc_dposv_mixed(n, _p(A), _ld(A), _p(b), tol, max_iter, _p(x), _p(eta))
+    it = lib().orc_dposv_mixed(n, _p(A), _ld(A), _p(b), tol, max_iter, prec, _p(x), _p(eta))
     return x, it, float(eta[0])
 
 
@@ -245,3 +280,26 @@ def batch_ric_trf(A, B, Q, R, PN, N, nthreads=0):
     info = np.zeros(bsz, dtype=np.int32)
     used = lib().orc_batch_ric_trf(bsz, nx, nu, N, *[_p(c) for c in conv], _p(F), info.ctypes.data_as(_ip), nthreads)
     return np.swapaxes(F, 2, 3), info, used
+
+
+def batch_dposv_mixed(mats, rhs, tol=1e-12, max_iter=10, prec=FP32, nthreads=0):
+    """Uneven batch of mixed-precision solves: lists of (n,n) matrices and
+    (n,nrhs) right-hand sides.  Returns (list of X, iters, eta, threads)."""
+    bsz = len(mats)
+    ns = np.array([m.shape[0] for m in mats], dtype=np.int32)
+    nrhs = int(np.asarray(rhs[0]).reshape(ns[0], -1).shape[1]) if bsz else 1
+    offA = np.zeros(bsz, dtype=np.int64)
+    offv = np.zeros(bsz, dtype=np.int64)
+    offA[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+    offv[1:] = np.cumsum(ns.astype(np.int64) * nrhs)[:-1]
+    Aall = np.concatenate([np.asarray(m, dtype=np.float64).ravel(order="F") for m in mats]) if bsz else np.zeros(1)
+    Ball = np.concatenate([np.asarray(v, dtype=np.float64).reshape(m.shape[0], nrhs).ravel(order="F")
+                           for m, v in zip(mats, rhs)]) if bsz else np.zeros(1)
+    X = np.zeros_like(Ball)
+    iters = np.zeros(max(bsz, 1), dtype=np.int32)
+    eta = np.zeros(max(bsz, 1))
+    used = lib().orc_batch_dposv_mixed(bsz, ns.ctypes.data_as(_ip), offA.ctypes.data_as(_lp), offv.ctypes.data_as(_lp),
+                                       _p(Aall), _p(Ball), nrhs, tol, max_iter, prec, _p(X),
+                                       iters.ctypes.data_as(_ip), _p(eta), nthreads)
+    Xs = [X[offv[i]:offv[i] + int(ns[i]) * nrhs].reshape(int(ns[i]), nrhs, order="F") for i in range(bsz)]
+    return Xs, iters[:bsz], eta[:bsz], used

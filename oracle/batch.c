@@ -24,6 +24,11 @@ int orc_ric_trf(int nx, int nu, int N, const double *A, int lda,
                 const double *B, int ldb, const double *Q, int ldq,
                 const double *R, int ldr, const double *PN, int ldp,
                 double *F);
+int orc_mixed_factor(int n, const double *A, int lda, int prec, float *L,
+                     int ldl, double *s);
+int orc_mixed_refine(int n, const double *A, int lda, const float *L32,
+                     int ldl, const double *s, const double *b, double tol,
+                     int max_iter, double *x, double *eta_out);
 
 static int set_threads(int nthreads) {
 #ifdef _OPENMP
@@ -104,5 +109,46 @@ int orc_batch_ric_trf(int batch, int nx, int nu, int N, const double *A,
     info[b] = orc_ric_trf(nx, nu, N, A + b * sa, nx, B + b * sbb, nx,
                           Q + b * sa, nx, R + b * sr, nu, PN + b * sa, nx,
                           F + b * sf);
+  return used;
+}
+
+/* Batch of mixed-precision solves A_b X_b = B_b (orc_mixed_factor once per
+ * instance, orc_mixed_refine per right-hand side).  Instance b: A at
+ * A + offA[b] (n_b x n_b, ld n_b), B and X at + offv[b] (n_b x nrhs, ld n_b).
+ * iters[b] = the largest number of corrections over the right-hand sides, or
+ * -1 (factorization failed) or -2 (some right-hand side gave up); eta[b] =
+ * the largest final backward error.  Returns the number of threads used. */
+int orc_batch_dposv_mixed(int batch, const int *n, const long long *offA,
+                          const long long *offv, const double *A,
+                          const double *B, int nrhs, double tol, int max_iter,
+                          int prec, double *X, int *iters, double *eta,
+                          int nthreads) {
+  int used = set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int b = 0; b < batch; ++b) {
+    const int nb = n[b];
+    float *L = (float *)malloc(sizeof(float) * ((size_t)nb * nb + 1));
+    double *s = (double *)malloc(sizeof(double) * ((size_t)nb + 1));
+    iters[b] = -3;
+    eta[b] = 0.0;
+    if (L && s) {
+      if (orc_mixed_factor(nb, A + offA[b], nb, prec, L, nb, s)) {
+        iters[b] = -1;
+      } else {
+        int it = 0;
+        for (int c = 0; c < nrhs; ++c) {
+          double e = 0.0;
+          const int r = orc_mixed_refine(nb, A + offA[b], nb, L, nb, s,
+                                         B + offv[b] + (size_t)c * nb, tol,
+                                         max_iter, X + offv[b] + (size_t)c * nb, &e);
+          if (e > eta[b] || e != e) eta[b] = e;
+          if (r < 0 || it < 0) it = it < 0 ? it : r; else if (r > it) it = r;
+        }
+        iters[b] = it;
+      }
+    }
+    free(L);
+    free(s);
+  }
   return used;
 }

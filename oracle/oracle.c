@@ -264,39 +264,122 @@ void orc_spotrs_l(int n, const float *L, int ldl, const float *b, float *x) {
   }
 }
 
-/* Mixed-precision solve with FP64 iterative refinement, for one right-hand
- * side: factor fl32(A) in single precision, x0 = solve32(fl32(b)); then
- * repeat r = b - A*x (FP64, lower triangle of A), stop if the backward
- * error of x is <= tol, else d = solve32(fl32(r)) and x = x + d (FP64).
- * Returns the number of refinement updates applied (>= 0), -1 if the
- * single-precision factorization fails, or -2 if tol is not reached within
- * max_iter updates.  eta_out receives the final backward error. */
-int orc_dposv_mixed(int n, const double *A, int lda, const double *b,
-                    double tol, int max_iter, double *x, double *eta_out) {
-  float *A32 = (float *)calloc((size_t)n * n + 1, sizeof(float));
-  float *L32 = (float *)malloc(sizeof(float) * (size_t)n * n);
-  float *v32 = (float *)malloc(sizeof(float) * (size_t)n);
-  float *d32 = (float *)malloc(sizeof(float) * (size_t)n);
-  double *r = (double *)malloc(sizeof(double) * (size_t)n);
-  int ret = 0;
-  if (!A32 || !L32 || !v32 || !d32 || !r) { ret = -3; goto done; }
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) EL(A32, n, i, j) = (float)EL(A, lda, i, j);
-  if (orc_spotrf_l(n, A32, n, L32, n)) { ret = -1; goto done; }
-  for (int i = 0; i < n; ++i) v32[i] = (float)b[i];
-  orc_spotrs_l(n, L32, n, v32, d32);
-  for (int i = 0; i < n; ++i) x[i] = (double)d32[i];
-  for (int it = 0;; ++it) {
-    double eta = orc_berr(n, A, lda, x, b);
-    if (eta_out) *eta_out = eta;
-    if (eta <= tol) { ret = it; break; }
-    if (it >= max_iter) { ret = -2; break; }
-    orc_dsymv_l(n, -1.0, A, lda, x, 1.0, b, r);
-    for (int i = 0; i < n; ++i) v32[i] = (float)r[i];
-    orc_spotrs_l(n, L32, n, v32, d32);
-    for (int i = 0; i < n; ++i) x[i] += (double)d32[i];
+/* IEEE binary16 value nearest to the binary32 value x (ties to even), as a
+ * float.  Written from the format's definition: 11 significant bits, least
+ * exponent -14 (subnormal quantum 2^-24), largest finite 65504. */
+float orc_fl16(float x) {
+  if (x != x) return x;
+  const float ax = fabsf(x);
+  if (ax >= 65520.0f) return copysignf(INFINITY, x); /* at/above the midpoint to 2^16 */
+  if (ax < 6.103515625e-05f) {                      /* below 2^-14: fixed quantum */
+    return copysignf(rintf(ax * 16777216.0f) / 16777216.0f, x);
   }
-done:
-  free(A32); free(L32); free(v32); free(d32); free(r);
+  int e;
+  frexpf(ax, &e);                        /* ax = m 2^e, m in [0.5, 1) */
+  const float q = ldexpf(1.0f, e - 11);  /* spacing of 11-bit significands */
+  return copysignf(rintf(ax / q) * q, x);
+}
+
+/* Power-of-two diagonal scaling of the mixed-precision solve (not from the
+ * paper): s_i = 2^-floor(e_i / 2) where a_ii = m 2^e_i, m in [0.5, 1), so
+ * that s_i^2 a_ii lies in [0.5, 2) and S A S (S = diag(s)) is formed without
+ * rounding.  s_i = 1 where a_ii is not a positive finite number. */
+void orc_mixed_scale(int n, const double *A, int lda, double *s) {
+  for (int i = 0; i < n; ++i) {
+    const double d = EL(A, lda, i, i);
+    s[i] = 1.0;
+    if (d > 0.0 && isfinite(d)) {
+      int e;
+      frexp(d, &e);
+      s[i] = ldexp(1.0, -(int)floor(e / 2.0));
+    }
+  }
+}
+
+/* Low-precision Cholesky factor of the scaled matrix fl32(S A S), lower
+ * triangle of A read.  prec 1: every operation in binary32.  prec 2: the
+ * same, except that both factors of every product in the downdate sums are
+ * first rounded to binary16 (the products themselves are exact in binary32).
+ * Returns 0 or the 1-based index of the first pivot that is not > 0. */
+int orc_mixed_factor(int n, const double *A, int lda, int prec, float *L,
+                     int ldl, double *s) {
+  orc_mixed_scale(n, A, lda, s);
+  for (int j = 0; j < n; ++j) {
+    float d = (float)(EL(A, lda, j, j) * s[j] * s[j]);
+    for (int k = 0; k < j; ++k) {
+      const float u = prec == 2 ? orc_fl16(EL(L, ldl, j, k)) : EL(L, ldl, j, k);
+      d -= u * u;
+    }
+    if (!(d > 0.0f)) return j + 1;
+    const float ljj = sqrtf(d);
+    const float inv = 1.0f / ljj;
+    EL(L, ldl, j, j) = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      float t = (float)(EL(A, lda, i, j) * s[i] * s[j]);
+      for (int k = 0; k < j; ++k) {
+        const float a = prec == 2 ? orc_fl16(EL(L, ldl, i, k)) : EL(L, ldl, i, k);
+        const float b = prec == 2 ? orc_fl16(EL(L, ldl, j, k)) : EL(L, ldl, j, k);
+        t -= a * b;
+      }
+      EL(L, ldl, i, j) = t * inv;
+    }
+    for (int i = 0; i < j; ++i) EL(L, ldl, i, j) = 0.0f;
+  }
+  return 0;
+}
+
+/* Iterative refinement in FP64 for one right-hand side (not from the
+ * paper), given the low-precision factor L of S A S (orc_mixed_factor): a
+ * correction solves A d = r as d = S solve32(fl32(S r)).  x0 is the
+ * correction for r = b; then repeat: r = b - A x (FP64, lower triangle of A),
+ * eta = backward error of x; stop if eta <= tol; give up if max_iter
+ * corrections were applied or if eta did not decrease since the previous
+ * test (stagnation); else x = x + d.  Returns the number of corrections
+ * applied after x0 (>= 0) or -2 if refinement gives up; eta_out receives the
+ * last backward error. */
+int orc_mixed_refine(int n, const double *A, int lda, const float *L32,
+                     int ldl, const double *s, const double *b, double tol,
+                     int max_iter, double *x, double *eta_out) {
+  float *v32 = (float *)calloc((size_t)n + 1, sizeof(float));
+  float *d32 = (float *)calloc((size_t)n + 1, sizeof(float));
+  double *r = (double *)calloc((size_t)n + 1, sizeof(double));
+  int ret = -3;
+  if (v32 && d32 && r) {
+    for (int i = 0; i < n; ++i) v32[i] = (float)(s[i] * b[i]);
+    orc_spotrs_l(n, L32, ldl, v32, d32);
+    for (int i = 0; i < n; ++i) x[i] = s[i] * (double)d32[i];
+    double prev = INFINITY;
+    for (int it = 0;; ++it) {
+      const double eta = orc_berr(n, A, lda, x, b);
+      if (eta_out) *eta_out = eta;
+      if (eta <= tol) { ret = it; break; }
+      if (it >= max_iter || !(eta < prev)) { ret = -2; break; }
+      prev = eta;
+      orc_dsymv_l(n, -1.0, A, lda, x, 1.0, b, r);
+      for (int i = 0; i < n; ++i) v32[i] = (float)(s[i] * r[i]);
+      orc_spotrs_l(n, L32, ldl, v32, d32);
+      for (int i = 0; i < n; ++i) x[i] += s[i] * (double)d32[i];
+    }
+  }
+  free(v32); free(d32); free(r);
+  return ret;
+}
+
+/* Mixed-precision solve of A x = b (one right-hand side): orc_mixed_factor
+ * then orc_mixed_refine.  Returns the number of corrections after x0, -1 if
+ * the low-precision factorization fails, -2 if refinement gives up. */
+int orc_dposv_mixed(int n, const double *A, int lda, const double *b,
+                    double tol, int max_iter, int prec, double *x,
+                    double *eta_out) {
+  float *L32 = (float *)malloc(sizeof(float) * ((size_t)n * n + 1));
+  double *s = (double *)malloc(sizeof(double) * ((size_t)n + 1));
+  int ret = -3;
+  if (L32 && s) {
+    if (orc_mixed_factor(n, A, lda, prec, L32, n, s))
+      ret = -1;
+    else
+      ret = orc_mixed_refine(n, A, lda, L32, n, s, b, tol, max_iter, x, eta_out);
+  }
+  free(L32); free(s);
   return ret;
 }

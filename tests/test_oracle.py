@@ -346,6 +346,81 @@ def test_spotrf_small_integer_exact_in_fp32():
     assert info == 0 and np.array_equal(D.astype(float), L)
 
 
+def test_fl16_matches_ieee_binary16():
+    """The binary16 rounding against numpy's float16 conversion (an
+    independent implementation of the same IEEE definition)."""
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        rng.standard_normal(4000) * 10.0 ** rng.integers(-9, 6, 4000),
+        [0.0, -0.0, 1.0, 65504.0, 65519.0, 65520.0, -65520.0, 7e4, 2.0 ** -14, 2.0 ** -24,
+         2.0 ** -25, 3 * 2.0 ** -26, 2.0 ** -26, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, 2049.0, 2051.0],
+    ]).astype(np.float32)
+    for x in xs:
+        with np.errstate(over="ignore"):
+            want = float(np.float32(x).astype(np.float16))
+        got = oracle.fl16(x)
+        assert got == want or (np.isinf(got) and np.isinf(want) and np.sign(got) == np.sign(want)), (x, got, want)
+    assert np.isnan(oracle.fl16(np.nan))
+
+
+def test_mixed_scale_powers_of_two():
+    rng = np.random.default_rng(1)
+    d = 10.0 ** rng.uniform(-300, 300, 200)
+    A = np.diag(np.concatenate([d, [0.0, -3.0, 1.0, 2.0, 0.5]]))
+    s = oracle.mixed_scale(A)
+    m, e = np.frexp(s)
+    assert np.all(m == 0.5)  # exact powers of two
+    t = s[:200] ** 2 * d
+    assert np.all((t >= 0.5) & (t < 2.0))
+    assert list(s[200:]) == [1.0, 1.0, 1.0, 0.5, 1.0]
+
+
+def structured_integer_factor(n, seed=0, diag=(1.0, 2.0)):
+    """Lower L with power-of-two diagonal, 16x16 diagonal blocks bidiagonal
+    (+-1 on the subdiagonal), entries of -1, 0, 1 below the diagonal blocks.
+    The inverse of every diagonal block then has entries of magnitude <= 1
+    times powers of two, so blocked and unblocked Cholesky in binary32 and
+    binary16 arithmetic all reproduce L exactly."""
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(-1, 2, (n, n)).astype(np.float64), -1)
+    for b0 in range(0, n, 16):
+        b1 = min(n, b0 + 16)
+        L[b0:b1, b0:b1] = 0.0
+        for i in range(b0 + 1, b1):
+            L[i, i - 1] = rng.choice([-1.0, 1.0])
+    L[np.arange(n), np.arange(n)] = rng.choice(np.asarray(diag), n)
+    return L, L @ L.T
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_factor_exact_on_integer_factor(prec):
+    """A = L L^T with a small-integer L: the factor of S A S is S L exactly."""
+    L, A = structured_integer_factor(70, seed=3)
+    L32, s, info = oracle.mixed_factor(A, prec)
+    assert info == 0
+    assert np.array_equal(L32.astype(np.float64), s[:, None] * L)
+
+
+@pytest.mark.parametrize("n", [50, 200])
+def test_mixed_factor_backward_error(n):
+    """Backward error of the low-precision factors against the unit roundoff
+    of each format: FP32 within c n u32; FP16 operands within c n u16 and
+    visibly above the FP32 level (the half rounding is really applied)."""
+    ns, mats, rhs = synth.conditioned_batch(1, 1e2, seed=4, sizes=[n])
+    A = mats[0]
+    res = {}
+    for prec in (1, 2):
+        L32, s, info = oracle.mixed_factor(A, prec)
+        assert info == 0
+        As = s[:, None] * A * s[None, :]
+        L = L32.astype(np.float64)
+        res[prec] = np.linalg.norm(L @ L.T - As) / np.linalg.norm(As)
+        assert np.all(np.triu(L32, 1) == 0) and np.all(np.diag(L32) > 0)
+    assert res[1] < n * 2.0 ** -24
+    assert res[2] < n * 2.0 ** -11
+    assert res[2] > 10 * res[1]
+
+
 @pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
 def test_dposv_mixed_reaches_fp64_backward_error(cond):
     ns, mats, rhs = synth.conditioned_batch(1, cond, seed=4, sizes=[40])
@@ -363,6 +438,45 @@ def test_dposv_mixed_non_spd():
     A = np.diag([1.0, -1.0, 2.0])
     x, it, eta = oracle.dposv_mixed(A, np.ones(3))
     assert it == -1
+
+
+def test_dposv_mixed_fp16_by_condition():
+    """FP16 operands with scaling: converge at cond 1e2 (more corrections
+    than FP32), and the factorization breaks down at cond 1e6."""
+    ns, mats, rhs = synth.conditioned_batch(2, 1e2, seed=4, sizes=[60, 200])
+    for A, b in zip(mats, rhs):
+        x, it16, eta = oracle.dposv_mixed(A, b[:, 0], prec=2, max_iter=30)
+        _, it32, _ = oracle.dposv_mixed(A, b[:, 0], prec=1, max_iter=30)
+        assert 0 < it32 < it16 and eta <= 1e-12
+        assert eta == oracle.berr(A, x, b[:, 0])
+    ns, mats, rhs = synth.conditioned_batch(1, 1e6, seed=4, sizes=[200])
+    assert oracle.dposv_mixed(mats[0], rhs[0][:, 0], prec=2)[1] == -1
+
+
+def test_dposv_mixed_exact_and_give_up():
+    """Exact data: x0 is exact, no correction.  max_iter = 0 on a system
+    that needs corrections: gives up with the backward error of x0."""
+    L, A = structured_integer_factor(40, seed=5)
+    xt = np.random.default_rng(2).integers(-3, 4, 40).astype(float)
+    for prec in (1, 2):
+        x, it, eta = oracle.dposv_mixed(A, A @ xt, prec=prec)
+        assert it == 0 and eta == 0.0 and np.array_equal(x, xt)
+    ns, mats, rhs = synth.conditioned_batch(1, 1e4, seed=4, sizes=[60])
+    x, it, eta = oracle.dposv_mixed(mats[0], rhs[0][:, 0], max_iter=0)
+    assert it == -2 and eta > 1e-12 and eta == oracle.berr(mats[0], x, rhs[0][:, 0])
+
+
+def test_batch_dposv_mixed_matches_single():
+    ns, mats, rhs = synth.conditioned_batch(4, 1e3, seed=4, nrhs=3, sizes=[17, 64, 33, 90])
+    Xs, iters, eta, used = oracle.batch_dposv_mixed(mats, rhs, nthreads=2)
+    for i in range(4):
+        its, etas = [], []
+        for c in range(3):
+            x, it, e = oracle.dposv_mixed(mats[i], rhs[i][:, c])
+            assert np.array_equal(x, Xs[i][:, c])
+            its.append(it)
+            etas.append(e)
+        assert iters[i] == max(its) and eta[i] == max(etas)
 
 
 # ----------------------------------------------------------------- batched drivers
