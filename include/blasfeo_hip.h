@@ -336,6 +336,55 @@ int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
 int blasfeo_hip_plan_config(const blasfeo_hip_plan *plan, int *cfg_out);
 void blasfeo_hip_plan_destroy(blasfeo_hip_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Mixed-precision solves of a plan's batch (not part of the paper; built on
+ * its panel-major storage, §4.3, and blocked Cholesky, §4.6).  Per instance:
+ *   S = diag(s), s_p = 2^-floor(e_p / 2) where a_pp = m 2^e_p, m in [0.5, 1)
+ *       (exact scaling; s_p = 1 where a_pp is not positive and finite);
+ *   L32 = Cholesky factor of fl32(S A S) in single precision: prec 1 with
+ *       FP32 matrix-core products, prec 2 with binary16 operands and FP32
+ *       accumulation in the downdates;
+ *   x0 = S L32^-T L32^-1 fl32(S b); then in FP64: r = b - A x, per
+ *       right-hand side eta_c = |r_c|_inf / (|A|_inf |x_c|_inf + |b_c|_inf);
+ *       stop when every eta_c <= tol; give up after max_iter corrections or
+ *       when some eta_c did not decrease; else x_c += S L32^-T L32^-1
+ *       fl32(S r_c) on the columns with eta_c > tol.
+ * Arguments: A, B, X are the plan's matrix and vector arenas (same layout
+ * as blasfeo_hip_dposv_vbatched; A lower part read; the plan needs
+ * nrhs >= 1).  iters (int), berr (double) and fallback (int) are device
+ * arrays of `batch` entries:
+ *   iters[i]    corrections applied after x0 (largest over the columns),
+ *   berr[i]     largest final eta_c (+inf if the factorization failed),
+ *   fallback[i] 0 = converged, 1 = low-precision factorization failed
+ *               (non-positive pivot), 2 = refinement gave up.
+ * If L (a matrix arena) is not NULL, every instance with fallback[i] != 0
+ * is then solved again by the FP64 kernels of blasfeo_hip_dposv_vbatched:
+ * X_i and L_i receive the FP64 result and info[i] its potrf info.  info
+ * (may be NULL) is 0 for every other instance.  If L is NULL, X_i of a
+ * fallen-back instance holds the last iterate (factorization failure: X_i
+ * untouched).
+ * The first call allocates the plan's workspace for the FP32 factors
+ * (blasfeo_hip_plan_enable_mixed; 4 KiB per 16x16 block pair, about
+ * 2 n^2 + 32 n floats per instance) with hipMalloc; later calls allocate
+ * nothing.  Returns 0, -i for bad argument i (-1 also: plan without
+ * right-hand sides, or an order/nrhs whose working set exceeds the 160 KiB
+ * of LDS of a workgroup), or a HIP error.  Asynchronous on `stream`.
+ * ---------------------------------------------------------------------- */
+#define BLASFEO_HIP_FP32 1
+#define BLASFEO_HIP_FP16_SCALED 2
+int blasfeo_hip_plan_enable_mixed(blasfeo_hip_plan *plan,
+                                  long long *workspace_bytes);
+int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *plan, int prec,
+                                     double tol, int max_iter, const void *A,
+                                     const void *B, void *X, void *L,
+                                     int *info, int *iters, double *berr,
+                                     int *fallback, void *stream);
+/* The FP32 factor L32 of instance i (of S A S, lower triangle, zeros above)
+ * from the last mixed-precision call, into the column-major device array
+ * dst (leading dimension ldd >= n_i).  Asynchronous on `stream`. */
+int blasfeo_hip_plan_mixed_factor(const blasfeo_hip_plan *plan, int i,
+                                  float *dst, int ldd, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

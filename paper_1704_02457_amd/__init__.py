@@ -79,7 +79,12 @@ _SIGS = {
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
     "blasfeo_hip_plan_destroy": (None, [_p]),
+    "blasfeo_hip_plan_enable_mixed": (_i, [_p, ctypes.POINTER(_ll)]),
+    "blasfeo_hip_dposv_mixed_vbatched": (_i, [_p, _i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_mixed_factor": (_i, [_p, _i, _p, _i, _p]),
 }
+
+FP32, FP16_SCALED = 1, 2
 
 
 def lib():
@@ -429,6 +434,29 @@ class VbPlan:
 
     def set_graph(self, on):
         return check(lib().blasfeo_hip_plan_set_graph(self.handle, 1 if on else 0))
+
+    def enable_mixed(self):
+        """Allocate the mixed-precision workspace; returns its size in bytes."""
+        wb = ctypes.c_longlong()
+        check(lib().blasfeo_hip_plan_enable_mixed(self.handle, ctypes.byref(wb)))
+        return wb.value
+
+    def solve_mixed(self, A, B, X, iters, berr, fallback, prec=FP32, tol=1e-12, max_iter=10,
+                    L=None, info=None, stream=None):
+        """blasfeo_hip_dposv_mixed_vbatched: iters/fallback int32 and berr
+        float64 device tensors of `batch` entries; with L (a matrix arena)
+        the instances that fall back are re-solved in FP64."""
+        return check(lib().blasfeo_hip_dposv_mixed_vbatched(
+            self.handle, int(prec), float(tol), int(max_iter), _ptr(A), _ptr(B), _ptr(X), _ptr(L),
+            _ptr(info), _ptr(iters), _ptr(berr), _ptr(fallback), _stream(stream)))
+
+    def mixed_factor(self, i, stream=None):
+        """(n_i, n_i) float32 device tensor: the FP32 factor of S A_i S."""
+        torch = _torch()
+        n = int(self.ns[i])
+        out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        check(lib().blasfeo_hip_plan_mixed_factor(self.handle, int(i), out.data_ptr(), n, _stream(stream)))
+        return out.t()  # column-major storage
 
     def config(self):
         import numpy as np

@@ -372,4 +372,25 @@ __device__ __forceinline__ void pad_identity(d4 &T, int nv) {
   }
 }
 
+// Block of right-hand sides kept compact in LDS (16 rows x nrhs, row-major)
+// <-> T-tile with the right-hand side index as the column: register r of lane
+// (c, g) = buf[(g + 4r) * nrhs + c], zero for c >= nrhs.
+__device__ __forceinline__ void save_compact(double *buf, const d4 &y, int nrhs) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  if (c < nrhs) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) buf[(g + 4 * r) * nrhs + c] = y[r];
+  }
+}
+
+__device__ __forceinline__ d4 load_compact(const double *buf, int nrhs) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  d4 y;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] = (c < nrhs) ? buf[(g + 4 * r) * nrhs + c] : 0.0;
+  return y;
+}
+
 }  // namespace bh

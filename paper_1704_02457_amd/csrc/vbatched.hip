@@ -21,7 +21,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "common.hpp"
+#include "plan.hpp"
 
 namespace bh {
 
@@ -37,6 +37,7 @@ struct VbArgs {
   double *X;
   int nrhs;
   int *info;
+  const int *only;  // if not null, instance id runs only where only[id] != 0
 };
 
 __device__ __forceinline__ int cn_of(int n) { return (n + 3) & ~3; }
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
   if (t >= a.count) return;
   DiagLds &s = lds[w];
   const int id = a.ids[t];
+  if (a.only && a.only[id] == 0) return;
   const int n = a.n[id];
   const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
   const int l = lane_id();
@@ -195,23 +197,6 @@ __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
 
 // Dynamic LDS of k_vb_large: W_j tiles (nbmax x 256), compact y/x blocks
 // (nbmax x 16 x nrhs), the current V (256), diagonal scratch.
-__device__ __forceinline__ void save_compact(double *buf, const d4 &y, int nrhs) {
-  const int l = lane_id();
-  const int c = l & 15, g = l >> 4;
-  if (c < nrhs) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) buf[(g + 4 * r) * nrhs + c] = y[r];
-  }
-}
-
-__device__ __forceinline__ d4 load_compact(const double *buf, int nrhs) {
-  const int l = lane_id();
-  const int c = l & 15, g = l >> 4;
-  d4 y;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) y[r] = (c < nrhs) ? buf[(g + 4 * r) * nrhs + c] : 0.0;
-  return y;
-}
 
 // Gemm downdate of the upper block T(j,i) of the transposed factor:
 //   acc -= sum_{q<j} U(q,j)^T U(q,i),  U(q,x) read back from L,
@@ -254,6 +239,7 @@ __global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
   const int t = blockIdx.x;
   if (t >= a.count) return;
   const int id = a.ids[t];
+  if (a.only && a.only[id] == 0) return;
   const int n = a.n[id];
   const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
   const int nb = pm;
@@ -330,29 +316,6 @@ size_t large_lds_bytes(int nbmax, int nrhs) {
 
 using namespace bh;
 
-struct blasfeo_hip_plan {
-  int batch = 0, nrhs = 0;
-  std::vector<int> n;
-  std::vector<long long> moff, voff;  // bytes
-  long long mat_bytes = 0, vec_bytes = 0;
-  int *d_n = nullptr;
-  long long *d_moff = nullptr, *d_voff = nullptr;
-  int *d_ids = nullptr;
-  struct Bucket {
-    int kind;   // 1..4: small kernel with NB = kind; 0: large kernel
-    int first;  // into the id list
-    int count;
-    int nbmax;  // large kernel: blocks of the largest instance
-    int cfg;    // small: waves per block (1, 2, 4); large: waves per instance (4, 8)
-  };
-  std::vector<Bucket> buckets;
-  int use_graph = 1;
-  bool have_graph = false;
-  const void *key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cap = nullptr;
-};
 
 static void drop_graph(blasfeo_hip_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -373,7 +336,7 @@ static void launch_small(const VbArgs &a, int vw, hipStream_t st) {
 
 static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Bucket &bk,
                          const double *A, double *L, const double *B, double *X,
-                         int *info, hipStream_t st) {
+                         int *info, hipStream_t st, const int *only = nullptr) {
   if (bk.count == 0) return 0;
   VbArgs a;
   a.ids = p->d_ids + bk.first;
@@ -387,6 +350,7 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
   a.X = X;
   a.nrhs = p->nrhs;
   a.info = info;
+  a.only = only;
   switch (bk.kind) {
     case 1: launch_small<1>(a, bk.cfg, st); break;
     case 2: launch_small<2>(a, bk.cfg, st); break;
@@ -405,13 +369,14 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
   return launch_status();
 }
 
-static int launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
-                      const double *B, double *X, int *info, hipStream_t st) {
+int bh::launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
+                   const double *B, double *X, int *info, hipStream_t st,
+                   const int *only) {
   // the large instances first: they are the longest (LPT)
   for (int pass = 0; pass < 2; ++pass)
     for (const auto &bk : p->buckets) {
       if ((pass == 0) != (bk.kind == 0)) continue;
-      int e = launch_bucket(p, bk, A, L, B, X, info, st);
+      int e = launch_bucket(p, bk, A, L, B, X, info, st, only);
       if (e) return e;
     }
   return 0;
@@ -623,6 +588,9 @@ void blasfeo_hip_plan_destroy(blasfeo_hip_plan *p) {
   if (p->d_voff) (void)hipFree(p->d_voff);
   if (p->d_ids) (void)hipFree(p->d_ids);
   if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->d_woff) (void)hipFree(p->d_woff);
+  if (p->d_mx_ids) (void)hipFree(p->d_mx_ids);
   delete p;
 }
 

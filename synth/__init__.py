@@ -195,3 +195,20 @@ def small_integer_factor(n, seed=11, diag=(1.0, 2.0, 4.0), off=3):
     L = np.tril(rng.integers(-off, off + 1, (n, n)).astype(np.float64), -1)
     L[np.arange(n), np.arange(n)] = rng.choice(np.asarray(diag, dtype=np.float64), n)
     return L, L @ L.T
+
+
+def structured_integer_factor(n, seed=0, diag=(1.0, 2.0)):
+    """Lower L with power-of-two diagonal, 16x16 diagonal blocks bidiagonal
+    (+-1 on the subdiagonal), entries of -1, 0, 1 below the diagonal blocks.
+    The inverse of every diagonal block then has entries of magnitude <= 1
+    times powers of two, so blocked and unblocked Cholesky in binary32 and
+    binary16 arithmetic all reproduce L exactly."""
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(-1, 2, (n, n)).astype(np.float64), -1)
+    for b0 in range(0, n, 16):
+        b1 = min(n, b0 + 16)
+        L[b0:b1, b0:b1] = 0.0
+        for i in range(b0 + 1, b1):
+            L[i, i - 1] = rng.choice([-1.0, 1.0])
+    L[np.arange(n), np.arange(n)] = rng.choice(np.asarray(diag), n)
+    return L, L @ L.T

@@ -375,27 +375,10 @@ def test_mixed_scale_powers_of_two():
     assert list(s[200:]) == [1.0, 1.0, 1.0, 0.5, 1.0]
 
 
-def structured_integer_factor(n, seed=0, diag=(1.0, 2.0)):
-    """Lower L with power-of-two diagonal, 16x16 diagonal blocks bidiagonal
-    (+-1 on the subdiagonal), entries of -1, 0, 1 below the diagonal blocks.
-    The inverse of every diagonal block then has entries of magnitude <= 1
-    times powers of two, so blocked and unblocked Cholesky in binary32 and
-    binary16 arithmetic all reproduce L exactly."""
-    rng = np.random.default_rng(seed)
-    L = np.tril(rng.integers(-1, 2, (n, n)).astype(np.float64), -1)
-    for b0 in range(0, n, 16):
-        b1 = min(n, b0 + 16)
-        L[b0:b1, b0:b1] = 0.0
-        for i in range(b0 + 1, b1):
-            L[i, i - 1] = rng.choice([-1.0, 1.0])
-    L[np.arange(n), np.arange(n)] = rng.choice(np.asarray(diag), n)
-    return L, L @ L.T
-
-
 @pytest.mark.parametrize("prec", [1, 2])
 def test_mixed_factor_exact_on_integer_factor(prec):
     """A = L L^T with a small-integer L: the factor of S A S is S L exactly."""
-    L, A = structured_integer_factor(70, seed=3)
+    L, A = synth.structured_integer_factor(70, seed=3)
     L32, s, info = oracle.mixed_factor(A, prec)
     assert info == 0
     assert np.array_equal(L32.astype(np.float64), s[:, None] * L)
@@ -456,7 +439,7 @@ def test_dposv_mixed_fp16_by_condition():
 def test_dposv_mixed_exact_and_give_up():
     """Exact data: x0 is exact, no correction.  max_iter = 0 on a system
     that needs corrections: gives up with the backward error of x0."""
-    L, A = structured_integer_factor(40, seed=5)
+    L, A = synth.structured_integer_factor(40, seed=5)
     xt = np.random.default_rng(2).integers(-3, 4, 40).astype(float)
     for prec in (1, 2):
         x, it, eta = oracle.dposv_mixed(A, A @ xt, prec=prec)
