@@ -167,10 +167,11 @@ double orc_berr(int n, const double *A, int lda, const double *x,
       rowabs += fabs(a);
     }
     double r = fabs(b[i] - s);
-    if (r > rmax) rmax = r;
-    if (rowabs > anorm) anorm = rowabs;
-    if (fabs(x[i]) > xmax) xmax = fabs(x[i]);
-    if (fabs(b[i]) > bmax) bmax = fabs(b[i]);
+    /* maxima propagate NaN: a NaN anywhere gives eta = NaN */
+    if (r > rmax || r != r) rmax = r;
+    if (rowabs > anorm || rowabs != rowabs) anorm = rowabs;
+    if (fabs(x[i]) > xmax || x[i] != x[i]) xmax = fabs(x[i]);
+    if (fabs(b[i]) > bmax || b[i] != b[i]) bmax = fabs(b[i]);
   }
   double den = anorm * xmax + bmax;
   return den > 0.0 ? rmax / den : rmax;

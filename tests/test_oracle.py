@@ -278,6 +278,11 @@ def test_symv_and_berr_closed_forms():
     xx = bb.copy()
     xx[0] += 0.25
     assert oracle.berr(np.eye(3), xx, bb) == pytest.approx(0.25 / (2.0 + 2.0), rel=1e-15)
+    # a NaN anywhere makes the norm, and so eta, NaN (never a pass)
+    for k in range(3):
+        xn = xx.copy()
+        xn[k] = np.nan
+        assert np.isnan(oracle.berr(np.eye(3), xn, bb))
 
 
 # ----------------------------------------------------------------- Riccati
