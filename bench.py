@@ -138,6 +138,74 @@ def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
     return out
 
 
+def mixed_fp64_counts(ns, nrhs):
+    """FP64 path per system: potrf n^3/3 + forward/back solves 2 n^2 per rhs."""
+    ns = np.asarray(ns, dtype=np.float64)
+    return float(np.sum(ns ** 3 / 3.0 + ns ** 2 / 2.0 + ns / 6.0 + 2.0 * nrhs * ns ** 2))
+
+
+def bench_mixed(p, synth, torch, batch=16384, nrhs=4, reps=3, conds=(1e2, 1e4, 1e6), fp16_max_cond=1e3):
+    """The mixed-precision workload: 16384 SPD systems, n ~ U{128..384},
+    A = U diag(sigma) U^T with cond in {1e2, 1e4, 1e6}, 4 rhs; the FP32
+    (and, for cond <= 1e3, FP16-operand) factor with FP64 refinement to
+    eta <= 1e-12, against the plain FP64 plan on the same data."""
+    ns = synth.conditioned_sizes(batch, seed=4)
+    plan = p.VbPlan(ns, nrhs)
+    ws = plan.enable_mixed()
+    A, L = plan.mat_arena(), plan.mat_arena(fill=0.0)
+    B, X = plan.vec_arena(), plan.vec_arena()
+    t0 = time.perf_counter()
+    orth = synth.orthogonal_batch_device(ns, seed=4, nrhs=nrhs)
+    for n, (idx, U, Bn) in orth.items():
+        plan.scatter_rhs(n, idx, Bn, B)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    info = torch.zeros(batch, dtype=torch.int32, device=dev)
+    iters = torch.zeros(batch, dtype=torch.int32, device=dev)
+    fb = torch.zeros(batch, dtype=torch.int32, device=dev)
+    berr = torch.zeros(batch, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    fl64 = mixed_fp64_counts(ns, nrhs)
+    out = {"mixed_batch": batch, "mixed_nrhs": nrhs, "mixed_workspace_gb": round(ws / 1e9, 2),
+           "mixed_input_gen_s": round(gen_s, 1), "mixed_fp64_gflop": round(fl64 / 1e9, 1)}
+    tuned = False
+    for cond in conds:
+        for n, (idx, U, Bn) in orth.items():
+            plan.pack_class(n, idx, synth.conditioned_from_orthogonal(U, cond), A)
+        torch.cuda.synchronize()
+        if not tuned:
+            plan.autotune(A, L, B, X, info)
+            tuned = True
+        _, per = time_events(lambda: plan.solve(A, L, B, X, info), reps, 1, stream)
+        ms64 = float(np.median(per))
+        r = {"fp64_ms": round(ms64, 3), "fp64_solves_per_s": round(batch / ms64 * 1e3, 1),
+             "fp64_gflops": round(fl64 / ms64 / 1e6, 1), "fp64_failed": int((info != 0).sum().item())}
+        precs = [("fp32", p.FP32)] + ([("fp16", p.FP16_SCALED)] if cond <= fp16_max_cond else [])
+        for name, prec in precs:
+            def solve():
+                plan.solve_mixed(A, B, X, iters, berr, fb, prec=prec, tol=1e-12, max_iter=10, L=L, info=info)
+            _, per = time_events(solve, reps, 1, stream)
+            ms = float(np.median(per))
+            it = iters.cpu().numpy()
+            f = fb.cpu().numpy()
+            be = berr.cpu().numpy()
+            ok = f == 0
+            r.update({
+                f"{name}_ms": round(ms, 3),
+                f"{name}_solves_per_s": round(batch / ms * 1e3, 1),
+                f"{name}_speedup_vs_fp64": round(ms64 / ms, 3),
+                f"{name}_iters_hist": {int(k): int(v) for k, v in zip(*np.unique(it[ok], return_counts=True))},
+                f"{name}_max_berr": float(be[ok].max()) if ok.any() else None,
+                f"{name}_fallback": {"factor": int((f == 1).sum()), "refine": int((f == 2).sum())},
+                f"{name}_fp64_failed_after_fallback": int((info != 0).sum().item()),
+            })
+        out[f"mixed_cond_{cond:.0e}"] = r
+    del A, L, B, X, orth, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_events(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -248,6 +316,8 @@ def main():
         extra.update(bench_uneven(p, synth, torch))
         print("[bench] Riccati batch (4096 x N=20)", file=sys.stderr, flush=True)
         extra.update(bench_riccati(p, synth, torch))
+        print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
+        extra.update(bench_mixed(p, synth, torch))
 
     if args.calib_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

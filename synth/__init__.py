@@ -158,9 +158,18 @@ def conditioned_batch(batch, cond, seed=4, nmin=128, nmax=384, nrhs=4, sizes=Non
     return ns, mats, rhs
 
 
-def conditioned_batch_device(ns, cond, seed=4, nrhs=4, device="cuda"):
-    """Device version: per size class (ascending n) draw G (count,n,n) then
-    B (count,n,nrhs); U = QR(G).Q; A = U diag(sigma) U^T.  Returns n -> (idx, A, B)."""
+def conditioned_sizes(batch, seed=4, nmin=128, nmax=384):
+    """n ~ U{nmin..nmax} (the sizes of conditioned_batch)."""
+    return np.random.default_rng(seed).integers(nmin, nmax + 1, batch).astype(np.int32)
+
+
+def orthogonal_batch_device(ns, seed=4, nrhs=4, device="cuda"):
+    """Per size class (ascending n): G (count,n,n) randn, then B (count,n,nrhs)
+    randn; U = the orthogonal factor of G = U R.  U is computed by two passes
+    of Cholesky QR (G <- G R^-1 with R^T R = G^T G), which gives the Q of a
+    Householder QR up to the signs of its columns -- signs that cancel in
+    U diag(sigma) U^T.  Classes whose Gram matrix is too ill-conditioned for
+    Cholesky QR use Householder QR.  Returns n -> (idx, U, B)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(seed)
@@ -168,15 +177,39 @@ def conditioned_batch_device(ns, cond, seed=4, nrhs=4, device="cuda"):
     out = {}
     for n in np.unique(ns):
         idx = np.nonzero(ns == n)[0]
-        cnt = len(idx)
-        G = torch.randn((cnt, int(n), int(n)), device=device, dtype=torch.float64, generator=g)
-        B = torch.randn((cnt, int(n), nrhs), device=device, dtype=torch.float64, generator=g)
-        U, _ = torch.linalg.qr(G)
-        del G
-        s = torch.as_tensor(spectrum(int(n), cond), device=device, dtype=torch.float64)
-        A = torch.bmm(U * s[None, None, :], U.transpose(1, 2).contiguous())
-        A = 0.5 * (A + A.transpose(1, 2))
-        out[int(n)] = (idx, A, B)
+        cnt, n = len(idx), int(n)
+        G = torch.randn((cnt, n, n), device=device, dtype=torch.float64, generator=g)
+        B = torch.randn((cnt, n, nrhs), device=device, dtype=torch.float64, generator=g)
+        U = G
+        ok = True
+        for _ in range(2):
+            gram = torch.bmm(U.transpose(1, 2).contiguous(), U)
+            Lg, info = torch.linalg.cholesky_ex(gram)
+            if bool((info != 0).any()):
+                ok = False
+                break
+            U = torch.linalg.solve_triangular(Lg.transpose(1, 2).contiguous(), U, upper=True, left=False)
+        if not ok:
+            U, _ = torch.linalg.qr(G)
+        out[n] = (idx, U, B)
+    return out
+
+
+def conditioned_from_orthogonal(U, cond):
+    """A = U diag(sigma) U^T (symmetrized) for a (count,n,n) orthogonal U."""
+    import torch
+    n = U.shape[-1]
+    s = torch.as_tensor(spectrum(n, cond), device=U.device, dtype=U.dtype)
+    A = torch.bmm(U * s[None, None, :], U.transpose(1, 2).contiguous())
+    return 0.5 * (A + A.transpose(1, 2))
+
+
+def conditioned_batch_device(ns, cond, seed=4, nrhs=4, device="cuda"):
+    """Device version of conditioned_batch: n -> (idx, A, B) per size class
+    (ascending n), A = U diag(sigma) U^T with U from orthogonal_batch_device."""
+    out = {}
+    for n, (idx, U, B) in orthogonal_batch_device(ns, seed, nrhs, device).items():
+        out[n] = (idx, conditioned_from_orthogonal(U, cond), B)
     return out
 
 

@@ -192,3 +192,38 @@ def test_mixed_repeat_and_errors():
     plan0 = p.VbPlan([10, 20], 0)
     with pytest.raises(p.HipError):
         plan0.enable_mixed()
+
+
+def test_mixed_full_size_sampled():
+    """The mixed-precision workload at full size (16384 systems, n ~ U{128..384},
+    4 rhs, cond 1e4, FP32 factor) in the benchmark's launch configuration:
+    every system converges to eta <= 1e-12 with no fallback; 16 sampled
+    systems are checked against the oracle (backward error of the GPU's x,
+    correction counts, x against the FP64 solution)."""
+    note("mixed full size")
+    batch, nrhs, cond = 16384, 4, 1e4
+    ns = synth.conditioned_sizes(batch, seed=4)
+    plan = p.VbPlan(ns, nrhs)
+    A, B, X = plan.mat_arena(), plan.vec_arena(), plan.vec_arena()
+    orth = synth.orthogonal_batch_device(ns, seed=4, nrhs=nrhs)
+    for n, (idx, U, Bn) in orth.items():
+        plan.pack_class(n, idx, synth.conditioned_from_orthogonal(U, cond), A)
+        plan.scatter_rhs(n, idx, Bn, B)
+    L = plan.mat_arena(fill=0.0)
+    it, be, fb, info = run(plan, A, B, X, p.FP32, L=L)
+    assert np.all(fb == 0) and np.all(info == 0)
+    assert float(be.max()) <= TOL
+    rng = np.random.default_rng(3)
+    keys = sorted(orth)
+    for n in rng.choice(keys, 16, replace=False):
+        idx, U, Bn = orth[int(n)]
+        i = int(idx[0])
+        Ah = synth.conditioned_from_orthogonal(U[:1], cond)[0].cpu().numpy()
+        bh = Bn[0].cpu().numpy()
+        xg = plan.rhs(X, i).cpu().numpy()
+        for c in range(nrhs):
+            assert oracle.berr(Ah, xg[:, c], bh[:, c]) <= TOL + n * 2.0 ** -52
+        _, ito, _, _ = oracle.batch_dposv_mixed([Ah], [bh], tol=TOL, max_iter=10, nthreads=1)
+        assert abs(int(it[i]) - int(ito[0])) <= 1
+        xr = oracle.dpotrs_l(oracle.dpotrf_l(Ah)[0], bh)
+        assert np.abs(xg - xr).max() / np.abs(xr).max() <= 8.0 * n * cond * TOL
