@@ -304,8 +304,10 @@ int blasfeo_hip_dric_trf_batched(int batch, int nx, int nu, int N,
  * wavefront per instance; n > 64: one workgroup per instance, largest
  * first), records one kernel launch per class into a hipGraph on the first
  * execution with a given set of pointers, and replays that graph afterwards.
- * Plan creation allocates a small device table (orders, offsets, class
- * lists) with hipMalloc; execution allocates nothing.
+ * Plan creation allocates with hipMalloc a small device table (orders,
+ * offsets, class lists) and, for the instances with n > 64, a workspace of
+ * 2 KiB per 16-row block (the inverses of the diagonal blocks, kept for the
+ * back substitution); execution allocates nothing.
  * ---------------------------------------------------------------------- */
 typedef struct blasfeo_hip_plan blasfeo_hip_plan;
 
@@ -332,8 +334,15 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *plan, const void *A, void *L,
 /* on = 0 executes with plain launches instead of the captured graph. */
 int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
 /* Writes the chosen configuration of every size class to cfg_out (may be
- * NULL) and returns the number of classes. */
+ * NULL) and returns the number of classes.  Classes 0..3 (n <= 16, 32, 48,
+ * 64): wavefronts per workgroup, 1, 2 or 4.  Class 4 (n > 64): waves per
+ * instance, 4, 8 or 16, plus 100 for the variant that stages each block
+ * column of the factor in LDS (104, 108, 116). */
 int blasfeo_hip_plan_config(const blasfeo_hip_plan *plan, int *cfg_out);
+/* Sets the configuration of every size class (count = the number of
+ * classes; values as above); drops the captured graph.  Returns 0, -2 for
+ * an invalid value, -3 for a wrong count. */
+int blasfeo_hip_plan_set_config(blasfeo_hip_plan *plan, const int *cfg, int count);
 void blasfeo_hip_plan_destroy(blasfeo_hip_plan *plan);
 
 /* ------------------------------------------------------------------------

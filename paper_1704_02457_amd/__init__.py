@@ -78,6 +78,7 @@ _SIGS = {
     "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
+    "blasfeo_hip_plan_set_config": (_i, [_p, _p, _i]),
     "blasfeo_hip_plan_destroy": (None, [_p]),
     "blasfeo_hip_plan_enable_mixed": (_i, [_p, ctypes.POINTER(_ll)]),
     "blasfeo_hip_dposv_mixed_vbatched": (_i, [_p, _i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
@@ -457,6 +458,11 @@ class VbPlan:
         out = torch.empty((n, n), dtype=torch.float32, device="cuda")
         check(lib().blasfeo_hip_plan_mixed_factor(self.handle, int(i), out.data_ptr(), n, _stream(stream)))
         return out.t()  # column-major storage
+
+    def set_config(self, cfg):
+        import numpy as np
+        arr = np.ascontiguousarray(np.asarray(cfg, dtype=np.int32))
+        return check(lib().blasfeo_hip_plan_set_config(self.handle, arr.ctypes.data_as(ctypes.c_void_p), len(arr)))
 
     def config(self):
         import numpy as np

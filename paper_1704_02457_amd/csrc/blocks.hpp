@@ -92,6 +92,69 @@ __device__ __forceinline__ void bstore(brsrc r, int voff, int soff, double x) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
 }
 
+// A square panel-major matrix of order n (origin at its first element)
+// addressed through a buffer descriptor: block (i, j) of 16x16 starts at
+// byte i * pst + j * 2048 (pst = 16 cn 8 bytes per panel), so the lane part
+// of a T-tile access is the same 8 * lane for every block.
+struct PMat {
+  brsrc r;
+  int pst;
+  int n;
+};
+
+__device__ __forceinline__ PMat make_pmat(const double *p, int n, int cn) {
+  const int pm = (n + 15) >> 4;
+  return PMat{make_rsrc(p, 8LL * (pm * 16LL * cn + n)), 16 * cn * 8, n};
+}
+
+// T-tile of block (i, j)^T: register r of lane (c, g) = M[16i + c][16j + g + 4r];
+// zero outside the matrix and, if lower, above its diagonal.
+__device__ __forceinline__ d4 pm_ldT(const PMat &m, int i, int j, bool lower) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int row = 16 * i + c;
+  const int base = i * m.pst + j * 2048;
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int col = 16 * j + g + 4 * r;
+    const bool ok = row < m.n && col < m.n && (!lower || row >= col);
+    const double x = bload(m.r, 8 * l, base + 512 * r);
+    t[r] = ok ? x : 0.0;
+  }
+  return t;
+}
+
+// T-tile of block (i, j) itself: register r of lane (c, g) = M[16i + g + 4r][16j + c].
+__device__ __forceinline__ d4 pm_ldN(const PMat &m, int i, int j) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int col = 16 * j + c;
+  const int base = i * m.pst + j * 2048;
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * i + g + 4 * r;
+    const double x = bload(m.r, 128 * c + 8 * g, base + 32 * r);
+    t[r] = (row < m.n && col < m.n) ? x : 0.0;
+  }
+  return t;
+}
+
+// Stores a T-tile holding block (i, j)^T, masked to the matrix and, if
+// lower, to its lower triangle.
+__device__ __forceinline__ void pm_stT(const PMat &m, int i, int j, const d4 &t, bool lower) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int row = 16 * i + c;
+  const int base = i * m.pst + j * 2048;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int col = 16 * j + g + 4 * r;
+    if (row < m.n && col < m.n && (!lower || row >= col)) bstore(m.r, 8 * l, base + 512 * r, t[r]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Generic (any offset, any bounds) accesses.  A "view" is a panel-major
 // matrix with its sub-matrix origin (ai, aj) and the sub-matrix extent.

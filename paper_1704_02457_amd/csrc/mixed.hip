@@ -201,66 +201,53 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// diagonal scaling s_p = 2^-floor(e/2) for a_pp = m 2^e (1 if a_pp is not
+// positive and finite): s_p^2 a_pp lies in [0.5, 2), the scaling is exact
+__device__ __forceinline__ double pow2_scale(double d) {
+  if (!(d > 0.0 && d <= 1.79769313486231570815e308)) return 1.0;
+  int e;
+  (void)frexp(d, &e);
+  return ldexp(1.0, -(e >> 1));
+}
+
 template <int LW>
-struct MxLds {
-  DiagLds diag;                 // wave 0: diagonal block
-  double tr[LW][16 * 17];       // per wave: transposes
-  float vsh[256];               // V_j for all waves
-  double eta[16], eprev[16];    // backward error per right-hand side
-  double rmax[16], xmax[16], bmax[16];
-  double anorm;
+struct FacLds {
+  DiagLds diag;            // wave 0: diagonal block
+  double tr[LW][16 * 17];  // per wave: transposes
+  float vsh[256];          // V_j for all waves
+  double sc[512];          // scaling
   int info;
 };
 
+// Factorization of fl32(S A S) into the workspace tiles, one workgroup of LW
+// waves per instance, left-looking over block columns: wave 0 downdates and
+// factors the diagonal block (FP64 registers, rounded back to FP32), then
+// the waves share the column's off-diagonal blocks.  Little LDS, so that
+// many instances run on a CU at once.  fallback[id] = 1 if a pivot is not
+// positive, else 0.
 template <int LW, bool H>
-__global__ __launch_bounds__(64 * LW) void k_mx(MxArgs a, int nbmax) {
-  extern __shared__ double dyn[];
-  __shared__ MxLds<LW> s;
+__global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
+  __shared__ FacLds<LW> s;
   const int t = blockIdx.x;
   if (t >= a.count) return;
   const int id = a.ids[t];
   const int n = a.n[id];
-  const int nb = (n + 15) >> 4, cn = (n + 3) & ~3, ld = (n + 15) & ~15;
+  const int nb = (n + 15) >> 4, cn = (n + 3) & ~3;
   const int nt = nb * (nb + 1) / 2;
-  const int nr = a.nrhs;
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
   const int tid = threadIdx.x;
   constexpr int NTH = 64 * LW;
-  const int nv16 = 16 * nb;
-
-  // dynamic LDS: x, r (FP64, compact n16 x nr), row sums of |A|, scaling,
-  // the FP32 vector of the solve
-  double *x64 = dyn;
-  double *r64 = x64 + (long long)nbmax * 16 * nr;
-  double *arow = r64 + (long long)nbmax * 16 * nr;
-  double *sc = arow + nbmax * 16;
-  float *vz = reinterpret_cast<float *>(sc + nbmax * 16);
-
   const View A{const_cast<double *>(a.A + a.moff[id]), cn, 0, 0, n, n};
-  const double *Bb = a.B + a.voff[id];
   float *Ut = a.ws + a.woff[id];
   float *Lt = Ut + 256LL * nt;
   float *Vt = Ut + 512LL * nt;
   float *Wt = Vt + 256LL * nb;
   double *tr = s.tr[w];
-
-  for (int p = tid; p < nv16; p += NTH) {
-    double sp = 1.0;
-    if (p < n) {
-      const double d = A.p[pm_off(p, p, cn)];
-      if (d > 0.0 && d <= 1.79769313486231570815e308) {
-        int e;
-        (void)frexp(d, &e);
-        sp = ldexp(1.0, -(e >> 1));
-      }
-    }
-    sc[p] = sp;
-    arow[p] = 0.0;
-  }
+  double *sc = s.sc;
+  for (int p = tid; p < 16 * nb; p += NTH) sc[p] = p < n ? pow2_scale(A.p[pm_off(p, p, cn)]) : 1.0;
   if (tid == 0) s.info = 0;
   __syncthreads();
-
   // ---------------------------------------------------------------- factor
   for (int j = 0; j < nb; ++j) {
     if (w == 0) {
@@ -291,15 +278,66 @@ __global__ __launch_bounds__(64 * LW) void k_mx(MxArgs a, int nbmax) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
   }
-  if (s.info) {
-    if (tid == 0) {
-      a.fallback[id] = 1;
+  if (tid == 0) {
+    a.fallback[id] = s.info ? 1 : 0;
+    if (s.info) {
       a.iters[id] = 0;
       a.berr[id] = __builtin_inf();
       if (a.info) a.info[id] = 0;
     }
-    return;
   }
+}
+
+template <int LW>
+struct MxLds {
+  double tr[LW][16 * 17];       // per wave: transposes
+  double eprev[16];             // backward error per right-hand side
+  double rmax[16], xmax[16], bmax[16];
+  double anorm;
+};
+
+// FP64 iterative refinement on the factor that k_mx_fac left in the
+// workspace (instances with fallback[id] == 1 are skipped): one workgroup of
+// LW waves per instance, the iterate, residual and solve vectors in LDS.
+template <int LW>
+__global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
+  extern __shared__ double dyn[];
+  __shared__ MxLds<LW> s;
+  const int t = blockIdx.x;
+  if (t >= a.count) return;
+  const int id = a.ids[t];
+  if (a.fallback[id] == 1) return;
+  const int n = a.n[id];
+  const int nb = (n + 15) >> 4, cn = (n + 3) & ~3, ld = (n + 15) & ~15;
+  const int nt = nb * (nb + 1) / 2;
+  const int nr = a.nrhs;
+  const int w = threadIdx.x >> 6;
+  const int l = lane_id();
+  const int tid = threadIdx.x;
+  constexpr int NTH = 64 * LW;
+  const int nv16 = 16 * nb;
+
+  // dynamic LDS: x, r (FP64, compact n16 x nr), row sums of |A|, scaling,
+  // the FP32 vector of the solve
+  double *x64 = dyn;
+  double *r64 = x64 + (long long)nbmax * 16 * nr;
+  double *arow = r64 + (long long)nbmax * 16 * nr;
+  double *sc = arow + nbmax * 16;
+  float *vz = reinterpret_cast<float *>(sc + nbmax * 16);
+
+  const View A{const_cast<double *>(a.A + a.moff[id]), cn, 0, 0, n, n};
+  const double *Bb = a.B + a.voff[id];
+  float *Ut = a.ws + a.woff[id];
+  float *Lt = Ut + 256LL * nt;
+  float *Vt = Ut + 512LL * nt;
+  float *Wt = Vt + 256LL * nb;
+  double *tr = s.tr[w];
+
+  for (int p = tid; p < nv16; p += NTH) {
+    sc[p] = p < n ? pow2_scale(A.p[pm_off(p, p, cn)]) : 1.0;
+    arow[p] = 0.0;
+  }
+  __syncthreads();
 
   // |b_c|_inf
   for (int c = w; c < nr; c += LW) {
@@ -491,9 +529,9 @@ size_t mx_lds_bytes(int nbmax, int nrhs) {
   return (size_t)nbmax * 16 * (sizeof(double) * (2 * nrhs + 2) + sizeof(float) * nrhs);
 }
 
-template <int LW, bool H>
+template <int LW>
 static hipError_t mx_prepare(size_t lds) {
-  return hipFuncSetAttribute((const void *)k_mx<LW, H>,
+  return hipFuncSetAttribute((const void *)k_mx_ir<LW>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -516,7 +554,8 @@ __global__ void k_mx_factor(const float *ws, long long woff, int n, float *dst,
 
 using namespace bh;
 
-static const int kMxLW = 4;
+static const int kMxLW = 4;     // waves per instance, refinement
+static const int kMxFacLW = 1;  // waves per instance, factorization
 
 static int mx_enable(blasfeo_hip_plan *p) {
   if (p->ws) return 0;
@@ -545,8 +584,7 @@ static int mx_enable(blasfeo_hip_plan *p) {
     if (e == hipSuccess)
       e = hipMemcpy(p->d_mx_ids, ids.data(), p->batch * sizeof(int), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = mx_prepare<kMxLW, false>(lds);
-  if (e == hipSuccess) e = mx_prepare<kMxLW, true>(lds);
+  if (e == hipSuccess) e = mx_prepare<kMxLW>(lds);
   if (e != hipSuccess) {
     if (p->ws) (void)hipFree(p->ws);
     if (p->d_woff) (void)hipFree(p->d_woff);
@@ -613,9 +651,10 @@ int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
   a.info = info;
   const size_t lds = mx_lds_bytes(p->mx_nbmax, p->nrhs);
   if (prec == 2)
-    hipLaunchKernelGGL((k_mx<kMxLW, true>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
+    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, true>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
   else
-    hipLaunchKernelGGL((k_mx<kMxLW, false>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
+    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, false>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
+  hipLaunchKernelGGL((k_mx_ir<kMxLW>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
   int e = launch_status();
   if (e) return e;
   // FP64 solve of the instances that fell back

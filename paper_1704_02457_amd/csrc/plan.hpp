@@ -27,6 +27,8 @@ struct blasfeo_hip_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
+  double *wsw = nullptr;          // n > 64: inverse diagonal blocks (W_j tiles)
+  long long *d_wwoff = nullptr;   // per instance offset into wsw (doubles)
   // mixed-precision solves (allocated on first use)
   float *ws = nullptr;          // low-precision factors, per instance
   long long ws_bytes = 0;

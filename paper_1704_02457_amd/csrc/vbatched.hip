@@ -38,6 +38,8 @@ struct VbArgs {
   int nrhs;
   int *info;
   const int *only;  // if not null, instance id runs only where only[id] != 0
+  double *wsw;             // n > 64: W_j = V_j^T tiles of instance id at
+  const long long *wwoff;  //   wsw + wwoff[id] (256 doubles per block)
 };
 
 __device__ __forceinline__ int cn_of(int n) { return (n + 3) & ~3; }
@@ -222,20 +224,52 @@ __device__ __forceinline__ d4 downdate(const View &L, int j, int i, d4 acc) {
   return acc;
 }
 
+// Gemm downdate as above with the U(q,j) tiles of the column staged in LDS
+// (ul, one 16x16 T-tile per 256 doubles): one global tile load per update.
+template <int DU>
+__device__ __forceinline__ d4 downdate_staged(const double *ul, const View &L, int j,
+                                              int i, d4 acc) {
+  const int l = lane_id();
+  int q = 0;
+  for (; q + DU <= j; q += DU) {
+    d4 ui[DU];
+#pragma unroll
+    for (int e = 0; e < DU; ++e) ui[e] = load_tileT(L, 16 * i, 16 * (q + e), false);
+#pragma unroll
+    for (int e = 0; e < DU; ++e) {
+      d4 uj;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) uj[r] = ul[(q + e) * 256 + 64 * r + l];
+      acc = mfma_tn(neg4(uj), ui[e], acc);
+    }
+  }
+  for (; q < j; ++q) {
+    d4 uj;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) uj[r] = ul[q * 256 + 64 * r + l];
+    acc = mfma_tn(neg4(uj), load_tileT(L, 16 * i, 16 * q, false), acc);
+  }
+  return acc;
+}
+
 // One workgroup of LW waves per instance.  Block column j of L: wave 0
 // downdates and factors the diagonal block (and advances the forward
 // substitution); then all waves share the off-diagonal blocks of the column:
-// gemm downdate and U(j,i) = V_j^T T(j,i).
-template <int LW>
+// gemm downdate and U(j,i) = V_j^T T(j,i).  With ST, the column's U(q,j)
+// tiles are first copied to LDS by all waves, so that every later use (the
+// diagonal downdate, the forward substitution, every off-diagonal downdate)
+// reads them there: the re-reads of the left part of the factor, which
+// mostly miss the L2, are halved.
+template <int LW, bool ST>
 __global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
-  constexpr int DU = 2;
+  constexpr int DU = ST ? 4 : 2;
   extern __shared__ double dyn[];
   __shared__ DiagLds s;
   __shared__ double vsh[256];
   __shared__ int sinfo;
   const int nr = a.nrhs > 0 ? a.nrhs : 1;
-  double *wl = dyn;                          // nbmax * 256
-  double *yl = dyn + (long long)nbmax * 256;  // nbmax * 16 * nr
+  double *yl = dyn;                                // nbmax * 16 * nr
+  double *ul = dyn + (long long)nbmax * 16 * nr;   // ST: nbmax * 256
   const int t = blockIdx.x;
   if (t >= a.count) return;
   const int id = a.ids[t];
@@ -250,17 +284,52 @@ __global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
   double *dAb = L.p + (long long)pm * 16 * cn;
   const bool has_rhs = a.nrhs > 0;
   const double *Bb = has_rhs ? a.B + a.voff[id] : nullptr;
+  double *wl = a.wsw + a.wwoff[id];
   if (threadIdx.x == 0) sinfo = 0;
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     const int nv = min(16, n - 16 * j);
+    if constexpr (ST) {
+      for (int q = w; q < j; q += LW) {
+        const d4 u = load_tileT(L, 16 * j, 16 * q, false);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ul[q * 256 + 64 * r + l] = u[r];
+      }
+      __syncthreads();
+    }
+    auto ujq = [&](int q) {
+      if constexpr (ST) {
+        d4 u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u[r] = ul[q * 256 + 64 * r + l];
+        return u;
+      } else {
+        return load_tileT(L, 16 * j, 16 * q, false);
+      }
+    };
     if (w == 0) {
-      d4 t0 = downdate<DU>(L, j, j, load_tileT(A, 16 * j, 16 * j, true));
+      // diagonal downdate and forward substitution, one load of U(q,j) each
+      d4 t0 = load_tileT(A, 16 * j, 16 * j, true);
       d4 z = has_rhs ? load_rhs(Bb, ld, n, a.nrhs, j) : zero4();
-      if (has_rhs)
-        for (int q = 0; q < j; ++q)
-          z = mfma_tn(neg4(load_tileT(L, 16 * j, 16 * q, false)),
-                      load_compact(yl + (long long)q * 16 * nr, nr), z);
+      int q = 0;
+      if constexpr (!ST) {
+        for (; q + DU <= j; q += DU) {
+          d4 u[DU];
+#pragma unroll
+          for (int e = 0; e < DU; ++e) u[e] = ujq(q + e);
+#pragma unroll
+          for (int e = 0; e < DU; ++e) {
+            t0 = mfma_tn(neg4(u[e]), u[e], t0);
+            if (has_rhs)
+              z = mfma_tn(neg4(u[e]), load_compact(yl + (long long)(q + e) * 16 * nr, nr), z);
+          }
+        }
+      }
+      for (; q < j; ++q) {
+        const d4 u = ujq(q);
+        t0 = mfma_tn(neg4(u), u, t0);
+        if (has_rhs) z = mfma_tn(neg4(u), load_compact(yl + (long long)q * 16 * nr, nr), z);
+      }
       pad_identity(t0, nv);
       d4 V, W;
       const int inf = potrf_inv_tile_upper(t0, V, s, &W);
@@ -280,7 +349,12 @@ __global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) V[r] = vsh[64 * r + l];
     for (int i = j + 1 + w; i < nb; i += LW) {
-      const d4 t1 = downdate<DU>(L, j, i, load_tileT(A, 16 * i, 16 * j, false));
+      const d4 a0 = load_tileT(A, 16 * i, 16 * j, false);
+      d4 t1;
+      if constexpr (ST)
+        t1 = downdate_staged<DU>(ul, L, j, i, a0);
+      else
+        t1 = downdate<DU>(L, j, i, a0);
       store_tileT(L, 16 * i, 16 * j, mfma_tn(V, t1, zero4()), false);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -305,9 +379,9 @@ __global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
   if (a.info && threadIdx.x == 0) a.info[id] = sinfo;
 }
 
-size_t large_lds_bytes(int nbmax, int nrhs) {
+size_t large_lds_bytes(int nbmax, int nrhs, bool staged) {
   const int nr = nrhs > 0 ? nrhs : 1;
-  return sizeof(double) * ((size_t)nbmax * 256 + (size_t)nbmax * 16 * nr);
+  return sizeof(double) * ((size_t)nbmax * 16 * nr + (staged ? (size_t)nbmax * 256 : 0));
 }
 
 }  // namespace bh
@@ -351,19 +425,29 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
   a.nrhs = p->nrhs;
   a.info = info;
   a.only = only;
+  a.wsw = p->wsw;
+  a.wwoff = p->d_wwoff;
   switch (bk.kind) {
     case 1: launch_small<1>(a, bk.cfg, st); break;
     case 2: launch_small<2>(a, bk.cfg, st); break;
     case 3: launch_small<3>(a, bk.cfg, st); break;
     case 4: launch_small<4>(a, bk.cfg, st); break;
     default: {
-      const size_t lds = large_lds_bytes(bk.nbmax, p->nrhs);
-      if (bk.cfg == 16)
-        hipLaunchKernelGGL(k_vb_large<16>, dim3(bk.count), dim3(1024), lds, st, a, bk.nbmax);
-      else if (bk.cfg == 8)
-        hipLaunchKernelGGL(k_vb_large<8>, dim3(bk.count), dim3(512), lds, st, a, bk.nbmax);
-      else
-        hipLaunchKernelGGL(k_vb_large<4>, dim3(bk.count), dim3(256), lds, st, a, bk.nbmax);
+      const bool staged = bk.cfg >= 100;
+      const int lw = bk.cfg % 100;
+      const size_t lds = large_lds_bytes(bk.nbmax, p->nrhs, staged);
+      const dim3 g(bk.count), b(64 * lw);
+      if (staged) {
+        if (lw == 16) hipLaunchKernelGGL((k_vb_large<16, true>), g, b, lds, st, a, bk.nbmax);
+        else if (lw == 8) hipLaunchKernelGGL((k_vb_large<8, true>), g, b, lds, st, a, bk.nbmax);
+        else hipLaunchKernelGGL((k_vb_large<4, true>), g, b, lds, st, a, bk.nbmax);
+      } else {
+        if (lw == 16) hipLaunchKernelGGL((k_vb_large<16, false>), g, b, lds, st, a, bk.nbmax);
+        else if (lw == 8) hipLaunchKernelGGL((k_vb_large<8, false>), g, b, lds, st, a, bk.nbmax);
+        else if (lw == 4) hipLaunchKernelGGL((k_vb_large<4, false>), g, b, lds, st, a, bk.nbmax);
+        else if (lw == 2) hipLaunchKernelGGL((k_vb_large<2, false>), g, b, lds, st, a, bk.nbmax);
+        else hipLaunchKernelGGL((k_vb_large<1, false>), g, b, lds, st, a, bk.nbmax);
+      }
     }
   }
   return launch_status();
@@ -427,6 +511,13 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
     const int nbmax = big.empty() ? 0 : (p->n[big[0]] + 15) / 16;
     p->buckets.push_back({0, first, (int)big.size(), nbmax, 4});
   }
+  std::vector<long long> wwo(batch, 0);
+  long long wtot = 0;
+  for (int i = 0; i < batch; ++i)
+    if (p->n[i] > 64) {
+      wwo[i] = wtot;
+      wtot += 256LL * ((p->n[i] + 15) / 16);
+    }
   std::vector<long long> md(batch), vd(batch);
   for (int i = 0; i < batch; ++i) {
     md[i] = p->moff[i] / 8;
@@ -438,6 +529,10 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
   if (e == hipSuccess) e = hipMalloc(&p->d_moff, nb * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&p->d_voff, nb * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&p->d_ids, nb * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&p->d_wwoff, nb * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&p->wsw, (size_t)std::max(wtot, 1LL) * sizeof(double));
+  if (e == hipSuccess && batch > 0)
+    e = hipMemcpy(p->d_wwoff, wwo.data(), batch * sizeof(long long), hipMemcpyHostToDevice);
   if (e == hipSuccess && batch > 0) {
     e = hipMemcpy(p->d_n, p->n.data(), batch * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_moff, md.data(), batch * sizeof(long long), hipMemcpyHostToDevice);
@@ -447,15 +542,14 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e == hipSuccess && p->buckets.back().count > 0) {
     // the large kernel's dynamic LDS may exceed the default limit
-    const int lds = (int)large_lds_bytes(p->buckets.back().nbmax, nrhs);
-    e = hipFuncSetAttribute((const void *)k_vb_large<8>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_vb_large<16>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_vb_large<4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const int nbm = p->buckets.back().nbmax;
+    const void *ks[8] = {(const void *)k_vb_large<4, true>, (const void *)k_vb_large<8, true>,
+                         (const void *)k_vb_large<16, true>, (const void *)k_vb_large<1, false>,
+                         (const void *)k_vb_large<2, false>, (const void *)k_vb_large<4, false>,
+                         (const void *)k_vb_large<8, false>, (const void *)k_vb_large<16, false>};
+    for (int k = 0; k < 8 && e == hipSuccess; ++k)
+      e = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)large_lds_bytes(nbm, nrhs, k < 3));
   }
   if (e != hipSuccess) {
     blasfeo_hip_plan_destroy(p);
@@ -479,6 +573,23 @@ int blasfeo_hip_plan_layout(const blasfeo_hip_plan *p, long long *mat_off,
 int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *p, int on) {
   if (!p) return -1;
   p->use_graph = on ? 1 : 0;
+  drop_graph(p);
+  return 0;
+}
+
+static bool cfg_valid(int kind, int cfg) {
+  if (kind) return cfg == 1 || cfg == 2 || cfg == 4;
+  return cfg == 1 || cfg == 2 || cfg == 4 || cfg == 8 || cfg == 16 || cfg == 104 ||
+         cfg == 108 || cfg == 116;
+}
+
+int blasfeo_hip_plan_set_config(blasfeo_hip_plan *p, const int *cfg, int count) {
+  if (!p) return -1;
+  if (!cfg) return -2;
+  if (count != (int)p->buckets.size()) return -3;
+  for (int i = 0; i < count; ++i)
+    if (!cfg_valid(p->buckets[i].kind, cfg[i])) return -2;
+  for (int i = 0; i < count; ++i) p->buckets[i].cfg = cfg[i];
   drop_graph(p);
   return 0;
 }
@@ -549,9 +660,9 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
   for (auto &bk : p->buckets) {
     if (bk.count == 0) continue;
     const int cands_small[3] = {1, 2, 4};
-    const int cands_large[3] = {4, 8, 16};
+    const int cands_large[6] = {1, 2, 4, 8, 104, 108};
     const int *cands = bk.kind ? cands_small : cands_large;
-    const int nc = 3;
+    const int nc = bk.kind ? 3 : 6;
     float best = 1e30f;
     int best_cfg = bk.cfg;
     for (int ci = 0; ci < nc && !err; ++ci) {
@@ -591,6 +702,8 @@ void blasfeo_hip_plan_destroy(blasfeo_hip_plan *p) {
   if (p->ws) (void)hipFree(p->ws);
   if (p->d_woff) (void)hipFree(p->d_woff);
   if (p->d_mx_ids) (void)hipFree(p->d_mx_ids);
+  if (p->wsw) (void)hipFree(p->wsw);
+  if (p->d_wwoff) (void)hipFree(p->d_wwoff);
   delete p;
 }
 

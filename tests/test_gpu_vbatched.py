@@ -161,3 +161,17 @@ def test_vbatched_full_size_sampled():
     R = torch.bmm(Lall, Lall.transpose(1, 2).contiguous()) - An[:64]
     assert float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(An[:64])).max()) < 256 * 1e-15
     del rng
+
+
+@pytest.mark.parametrize("cfg", [4, 8, 16, 104, 108, 116])
+def test_vbatched_large_kernel_configs(cfg):
+    """Every launch configuration of the n > 64 class, with and without
+    right-hand sides, ragged orders up to the largest supported one."""
+    note("vbatched large cfg", cfg)
+    ns = [65, 80, 100, 127, 128, 129, 200, 256, 300, 383, 512]
+    for nrhs in (3, 0):
+        plan, mats, rhs, A, L, B, X, info = build(ns, nrhs, seed=cfg)
+        plan.set_config([2, 2, 2, 2, cfg])
+        assert list(plan.config()) == [2, 2, 2, 2, cfg]
+        plan.solve(A, L, B, X, info)
+        check_all(plan, mats, rhs, L, X, info, nrhs, f"cfg {cfg} nrhs {nrhs}")
