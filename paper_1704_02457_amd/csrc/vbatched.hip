@@ -509,7 +509,7 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
                      [&](int x, int y) { return p->n[x] > p->n[y]; });
     ids.insert(ids.end(), big.begin(), big.end());
     const int nbmax = big.empty() ? 0 : (p->n[big[0]] + 15) / 16;
-    p->buckets.push_back({0, first, (int)big.size(), nbmax, 4});
+    p->buckets.push_back({0, first, (int)big.size(), nbmax, 2});
   }
   std::vector<long long> wwo(batch, 0);
   long long wtot = 0;
