@@ -330,8 +330,8 @@ struct WaveLds {
   double inv[16];
 };
 
-// Scratch of potrf_inv_tile_upper: the two broadcast rows and a padded
-// 16x17 transpose buffer.
+// Scratch of potrf_inv_tile_upper: the pivots, the reciprocals and a padded
+// 16x17 transpose buffer (the pivot rows go through its first 32 doubles).
 struct DiagLds {
   double rowU[16];
   double rowW[16];
@@ -344,6 +344,17 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/sqrt(d) for d > 0: the hardware estimate, two Newton steps and one
+// residual correction (Markstein), within an ulp of the exact value and exact
+// when it is representable (d a power of 4).
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return fma(0.5 * r, fma(-d * r, r, 1.0), r);
 }
 
 // Upper Cholesky factorization of a T-tile together with the inverse of the
@@ -360,9 +371,12 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
 // the T-tile each).  Inside a panel the rank-1 downdates of T and updates of
 // S touch only the panel's rows; the panel's contribution to the rows below
 // is then one rank-4 MFMA for T and one for S (register b of a T-tile is the
-// MFMA operand of rows 4b..4b+3).  The pivot is fetched with readlane; the
-// pivot row of U and of W go through LDS once per pivot.  V is W^T (one LDS
-// transpose at the end).
+// MFMA operand of rows 4b..4b+3).  The pivot is fetched with readlane, the
+// pivot rows of U and W cross lanes once through LDS, and a wave's LDS
+// operations execute in order, so one wait per pivot suffices.  The chain
+// from one pivot to the next carries only 1/sqrt(d) (rsqrt_refined); the
+// diagonal sqrt(d) is formed for all 16 columns after the sweep.  V is W^T
+// (one LDS transpose at the end).
 __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
                                                     DiagLds &s,
                                                     d4 *Wout = nullptr) {
@@ -370,36 +384,36 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
   const int c = l & 15, g = l >> 4;
   int info = 0;
   d4 S = zero4(), W = zero4();
+  double *rowU = s.tr, *rowW = s.tr + 16;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * b + kk;
       const double d = readlane_d(T[b], k + 16 * kk);
-      const double ukk = sqrt(d);
       const bool ok = d > 0.0;
-      const double iv = ok ? 1.0 / ukk : 0.0;
+      const double iv = ok ? rsqrt_refined(d) : 0.0;
       if (!ok && info == 0) info = k + 1;
-      // row k of U and of W, valid in lane group kk
-      const double ukc = (c > k) ? T[b] * iv : (c == k ? ukk : 0.0);
+      if (l == 0) s.inv[k] = iv;
+      if (l == k) s.rowU[k] = d;  // pivot of column k, for the diagonal below
+      // row k of U (off the diagonal) and of W, valid in lane group kk
+      const double ukc = (c > k) ? T[b] * iv : 0.0;
       const double wkc = (((c == k) ? 1.0 : 0.0) - S[b]) * iv;
       const bool mine = g == kk;
       if (mine) {
-        s.rowU[c] = ukc;
-        s.rowW[c] = wkc;
+        rowU[c] = ukc;
+        rowW[c] = wkc;
       }
       T[b] = mine ? ukc : T[b];
       W[b] = mine ? wkc : W[b];
-      if (l == 0) s.inv[k] = iv;
       wave_sync();
       // rank-1 downdate of the panel rows below the pivot (groups g > kk)
-      const double rc = s.rowU[c];
-      const double rp = s.rowU[4 * b + g];
-      const double rw = s.rowW[c];
+      const double rc = rowU[c];
+      const double rp = rowU[4 * b + g];
+      const double rw = rowW[c];
       const bool below = g > kk;
       T[b] = (below && c > k) ? T[b] - rp * rc : T[b];
       S[b] = below ? S[b] + rp * rw : S[b];
-      wave_sync();
     }
     if (b < 3) {
       const double ub = T[b], wb = W[b];
@@ -412,7 +426,13 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
       }
     }
   }
+  // the diagonal of U: sqrt(d_c), correctly rounded (exact for squares)
+  wave_sync();
+  const double uc = sqrt(s.rowU[c]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[r] = (c == g + 4 * r) ? uc : T[r];
   if (Wout) *Wout = W;  // W = L^{-1} = V^T, itself a T-tile
+  wave_sync();
   // V = W^T through a padded LDS transpose
 #pragma unroll
   for (int r = 0; r < 4; ++r) s.tr[(g + 4 * r) * 17 + c] = W[r];

@@ -261,7 +261,7 @@ __device__ __forceinline__ d4 downdate_staged(const double *ul, const View &L, i
 // reads them there: the re-reads of the left part of the factor, which
 // mostly miss the L2, are halved.
 template <int LW, bool ST>
-__global__ __launch_bounds__(64 * LW) void k_vb_large(VbArgs a, int nbmax) {
+__global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) void k_vb_large(VbArgs a, int nbmax) {
   constexpr int DU = ST ? 4 : 2;
   extern __shared__ double dyn[];
   __shared__ DiagLds s;
