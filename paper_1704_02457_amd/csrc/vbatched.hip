@@ -224,6 +224,19 @@ __device__ __forceinline__ d4 downdate(const View &L, int j, int i, d4 acc) {
   return acc;
 }
 
+// Two block rows i0, i1 of column j at once: each U(q,j) is loaded once for
+// both, and twice as many independent loads are in flight per step.
+__device__ __forceinline__ void downdate_pair(const View &L, int j, int i0, int i1,
+                                              d4 &acc0, d4 &acc1) {
+  for (int q = 0; q < j; ++q) {
+    const d4 uj = load_tileT(L, 16 * j, 16 * q, false);
+    const d4 ua = load_tileT(L, 16 * i0, 16 * q, false);
+    const d4 ub = load_tileT(L, 16 * i1, 16 * q, false);
+    acc0 = mfma_tn(neg4(uj), ua, acc0);
+    acc1 = mfma_tn(neg4(uj), ub, acc1);
+  }
+}
+
 // Gemm downdate as above with the U(q,j) tiles of the column staged in LDS
 // (ul, one 16x16 T-tile per 256 doubles): one global tile load per update.
 template <int DU>
@@ -260,7 +273,7 @@ __device__ __forceinline__ d4 downdate_staged(const double *ul, const View &L, i
 // diagonal downdate, the forward substitution, every off-diagonal downdate)
 // reads them there: the re-reads of the left part of the factor, which
 // mostly miss the L2, are halved.
-template <int LW, bool ST>
+template <int LW, bool ST, bool PAIR = true>
 __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) void k_vb_large(VbArgs a, int nbmax) {
   constexpr int DU = ST ? 4 : 2;
   extern __shared__ double dyn[];
@@ -348,7 +361,17 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     d4 V;
 #pragma unroll
     for (int r = 0; r < 4; ++r) V[r] = vsh[64 * r + l];
-    for (int i = j + 1 + w; i < nb; i += LW) {
+    int i = j + 1 + w;
+    if constexpr (!ST && PAIR) {
+      for (; i + LW < nb; i += 2 * LW) {
+        d4 t0 = load_tileT(A, 16 * i, 16 * j, false);
+        d4 t1 = load_tileT(A, 16 * (i + LW), 16 * j, false);
+        downdate_pair(L, j, i, i + LW, t0, t1);
+        store_tileT(L, 16 * i, 16 * j, mfma_tn(V, t0, zero4()), false);
+        store_tileT(L, 16 * (i + LW), 16 * j, mfma_tn(V, t1, zero4()), false);
+      }
+    }
+    for (; i < nb; i += LW) {
       const d4 a0 = load_tileT(A, 16 * i, 16 * j, false);
       d4 t1;
       if constexpr (ST)
