@@ -43,6 +43,7 @@ __global__ __launch_bounds__(64) void k_ric_trf(RicArgs a) {
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int NLT = NXB * (NXB + 1) / 2;
   __shared__ DiagLds s;
+  __shared__ double xs[NXB * NB][256];  // X^T tiles, constant over the stages
   const long long b = blockIdx.x;
   if (b >= a.batch) return;
   const int l = lane_id();
@@ -55,20 +56,25 @@ __global__ __launch_bounds__(64) void k_ric_trf(RicArgs a) {
   R.p += b * a.sR;
   P.p += b * a.sP;
 
-  // X^T tiles: logical X^T(m, j) block, X = [B^T; 0; A^T] (padded rows)
-  d4 Xt[NXB][NB];
+  // X^T tiles: logical X^T(m, j) block, X = [B^T; 0; A^T] (padded rows),
+  // kept in LDS (they are read once per stage and would otherwise hold
+  // registers through the whole recursion)
 #pragma unroll
   for (int m = 0; m < NXB; ++m) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      if (j < NUB) {
-        // X(16j + q, 16m + p) = B(16m + p, 16j + q) for 16j + q < nu
-        Xt[m][j] = load_tileN(B, 16 * m, 16 * j);
-      } else {
-        Xt[m][j] = load_tileN(A, 16 * m, 16 * (j - NUB));
-      }
+      // X(16j + q, 16m + p) = B(16m + p, 16j + q) for 16j + q < nu
+      const d4 x = (j < NUB) ? load_tileN(B, 16 * m, 16 * j) : load_tileN(A, 16 * m, 16 * (j - NUB));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xs[m * NB + j][64 * r + l] = x[r];
     }
   }
+  auto Xt = [&](int m, int j) {
+    d4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = xs[m * NB + j][64 * r + l];
+    return x;
+  };
 
   // Lc_N = chol(P_N): register factorization of the NXB x NXB block
   d4 Ln[NLT];  // Ln(m,k), m >= k, logical Lc(m,k), index tix_up(k, m)
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(64) void k_ric_trf(RicArgs a) {
         for (int j = 0; j < NB; ++j) {
           d4 acc = zero4();
 #pragma unroll
-          for (int m = k; m < NXB; ++m) acc = mfma_tn(Ln[tix_up(k, m)], Xt[m][j], acc);
+          for (int m = k; m < NXB; ++m) acc = mfma_tn(Ln[tix_up(k, m)], Xt(m, j), acc);
           Ct[k][j] = acc;
         }
       // T(j,i) = blockdiag(R, I, Q)(j,i) + sum_k Ct(k,j)^T Ct(k,i)
