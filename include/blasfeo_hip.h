@@ -301,8 +301,8 @@ int blasfeo_hip_dric_trf_batched(int batch, int nx, int nu, int N,
  *     round_up(n_i, 16), at byte offset vec_off[i] of two vector arenas of
  *     vec_bytes bytes.
  * The plan sorts the instances into size classes (n <= 16, 32, 48, 64: one
- * wavefront per instance; n > 64: one workgroup per instance, largest
- * first), records one kernel launch per class into a hipGraph on the first
+ * wavefront per instance; 64 < n <= 192 and n > 192: one workgroup per
+ * instance, largest first), records one kernel launch per class into a hipGraph on the first
  * execution with a given set of pointers, and replays that graph afterwards.
  * Plan creation allocates with hipMalloc a small device table (orders,
  * offsets, class lists) and, for the instances with n > 64, a workspace of
@@ -335,9 +335,10 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *plan, const void *A, void *L,
 int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
 /* Writes the chosen configuration of every size class to cfg_out (may be
  * NULL) and returns the number of classes.  Classes 0..3 (n <= 16, 32, 48,
- * 64): wavefronts per workgroup, 1, 2 or 4.  Class 4 (n > 64): waves per
- * instance, 4, 8 or 16, plus 100 for the variant that stages each block
- * column of the factor in LDS (104, 108, 116). */
+ * 64): wavefronts per workgroup, 1, 2 or 4.  Classes 4 (192 < n <= 512)
+ * and 5 (64 < n <= 192): waves per instance, 1, 2, 4, 8 or 16, plus 100 for
+ * the variant that stages each block column of the factor in LDS (104, 108,
+ * 116). */
 int blasfeo_hip_plan_config(const blasfeo_hip_plan *plan, int *cfg_out);
 /* Sets the configuration of every size class (count = the number of
  * classes; values as above); drops the captured graph.  Returns 0, -2 for

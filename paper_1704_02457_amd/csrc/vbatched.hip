@@ -414,6 +414,9 @@ size_t large_lds_bytes(int nbmax, int nrhs, bool staged) {
 using namespace bh;
 
 
+// orders above this go to the second n > 64 class
+static const int kLargeSplit = 192;
+
 static void drop_graph(blasfeo_hip_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -523,16 +526,19 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
       if ((p->n[i] + 15) / 16 == kind) ids.push_back(i);
     p->buckets.push_back({kind, first, (int)ids.size() - first, kind, 2});
   }
-  {
+  // n > 64: two classes (n <= 192 and n > 192), each largest first and each
+  // with its own launch configuration (the larger instances favour more
+  // waves per instance)
+  for (int part = 0; part < 2; ++part) {
     const int first = (int)ids.size();
     std::vector<int> big;
     for (int i = 0; i < batch; ++i)
-      if (p->n[i] > 64) big.push_back(i);
+      if (p->n[i] > 64 && ((p->n[i] > kLargeSplit) == (part == 0))) big.push_back(i);
     std::stable_sort(big.begin(), big.end(),
                      [&](int x, int y) { return p->n[x] > p->n[y]; });
     ids.insert(ids.end(), big.begin(), big.end());
     const int nbmax = big.empty() ? 0 : (p->n[big[0]] + 15) / 16;
-    p->buckets.push_back({0, first, (int)big.size(), nbmax, 2});
+    p->buckets.push_back({0, first, (int)big.size(), nbmax, part == 0 ? 2 : 1});
   }
   std::vector<long long> wwo(batch, 0);
   long long wtot = 0;
@@ -563,9 +569,11 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
     if (e == hipSuccess) e = hipMemcpy(p->d_ids, ids.data(), batch * sizeof(int), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
-  if (e == hipSuccess && p->buckets.back().count > 0) {
+  int nbm = 0;
+  for (const auto &bk : p->buckets)
+    if (bk.kind == 0) nbm = std::max(nbm, bk.nbmax);
+  if (e == hipSuccess && nbm > 0) {
     // the large kernel's dynamic LDS may exceed the default limit
-    const int nbm = p->buckets.back().nbmax;
     const void *ks[8] = {(const void *)k_vb_large<4, true>, (const void *)k_vb_large<8, true>,
                          (const void *)k_vb_large<16, true>, (const void *)k_vb_large<1, false>,
                          (const void *)k_vb_large<2, false>, (const void *)k_vb_large<4, false>,

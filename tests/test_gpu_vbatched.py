@@ -92,7 +92,7 @@ def test_vbatched_graph_replay_and_autotune():
     plan.solve(A, L, B, X, info)
     check_all(plan, mats, rhs, L, X, info, 2, "graph new data")
     plan.autotune(A, L, B, X, info)
-    assert len(plan.config()) == 5
+    assert len(plan.config()) == 6
     plan.solve(A, L, B, X, info)
     check_all(plan, mats, rhs, L, X, info, 2, "after autotune")
 
@@ -171,7 +171,7 @@ def test_vbatched_large_kernel_configs(cfg):
     ns = [65, 80, 100, 127, 128, 129, 200, 256, 300, 383, 512]
     for nrhs in (3, 0):
         plan, mats, rhs, A, L, B, X, info = build(ns, nrhs, seed=cfg)
-        plan.set_config([2, 2, 2, 2, cfg])
-        assert list(plan.config()) == [2, 2, 2, 2, cfg]
+        plan.set_config([2, 2, 2, 2, cfg, cfg])
+        assert list(plan.config()) == [2, 2, 2, 2, cfg, cfg]
         plan.solve(A, L, B, X, info)
         check_all(plan, mats, rhs, L, X, info, nrhs, f"cfg {cfg} nrhs {nrhs}")
