@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
 // block's inverse (off-diagonal blocks) -- and stored (§4.6: LAPACK routines
 // written as BLAS-like kernels, block size = kernel size).
 struct PotrfLds {
-  WaveLds w;
+  DiagLds d;
   double V[64 * 4];  // inverse of the current diagonal block (T-tile)
   int info;
 };
@@ -153,11 +153,11 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
         t = mfma_tn(neg4(u), u, t);
       }
       pad_identity(t, nv);
-      const int inf = potrf_tile_upper(t, s.w.row, s.w.inv);
+      d4 v;
+      const int inf = potrf_inv_tile_upper(t, v, s.d);
       if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
       store_tileT(D, 16 * j, 16 * j, t, true);
-      if (dAb && l < nv) dAb[16 * j + l] = s.w.inv[l];
-      const d4 v = trtri_tile_upper(t, s.w.inv, s.w.ulds, s.w.row);
+      if (dAb && l < nv) dAb[16 * j + l] = s.d.inv[l];
 #pragma unroll
       for (int r = 0; r < 4; ++r) s.V[l * 4 + r] = v[r];
     }
@@ -182,6 +182,73 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
     __syncthreads();
   }
   if (info && threadIdx.x == 0) info[b] = s.info;
+}
+
+// m <= 16*NB <= 64: one wavefront per instance with the whole factor in
+// registers (the fused kernel's scheme on generic views): T(j,i) = C(i,j)^T
+// (+ the syrk term of syrk_potrf), then for each block row the diagonal
+// subroutine, U(j,i) = V^T T(j,i) and the trailing MFMA downdates; every
+// block is read and written once, with no barrier.
+template <int NB>
+__global__ __launch_bounds__(64) void k_potrf_reg(
+    int m, int k, View A, View B, View C, View D, double *dA, int *info,
+    long long sA, long long sB, long long sC, long long sD, long long sdA) {
+  A = at_batch(A, sA);
+  B = at_batch(B, sB);
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *dAb = dA ? dA + b * sdA : nullptr;
+  __shared__ DiagLds s;
+  const int l = lane_id();
+  constexpr int NT = NB * (NB + 1) / 2;
+  d4 T[NT];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) T[tix_up(j, i)] = load_tileT(C, 16 * i, 16 * j, i == j);
+  for (int k0 = 0; k0 < k; k0 += 4) {
+    double fa[NB], fb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      fa[i] = load_frag(A, 16 * i, k0);
+      fb[i] = load_frag(B, 16 * i, k0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) T[tix_up(j, i)] = mfma(fb[j], fa[i], T[tix_up(j, i)]);
+  }
+  int inf0 = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int nv = min(16, m - 16 * j);
+    if (nv <= 0) break;
+    d4 &Dj = T[tix_up(j, j)];
+    pad_identity(Dj, nv);
+    d4 V;
+    const int inf = potrf_inv_tile_upper(Dj, V, s);
+    if (inf && inf0 == 0) inf0 = 16 * j + inf;
+    store_tileT(D, 16 * j, 16 * j, Dj, true);
+    if (dAb && l < nv) dAb[16 * j + l] = s.inv[l];
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      T[tix_up(j, i)] = mfma_tn(V, T[tix_up(j, i)], zero4());
+      store_tileT(D, 16 * i, 16 * j, T[tix_up(j, i)], false);
+    }
+#pragma unroll
+    for (int q = j + 1; q < NB; ++q) {
+      const d4 nu = neg4(T[tix_up(j, q)]);
+#pragma unroll
+      for (int i = q; i < NB; ++i) T[tix_up(q, i)] = mfma_tn(nu, T[tix_up(j, i)], T[tix_up(q, i)]);
+    }
+  }
+  if (info && l == 0) info[b] = inf0;
+}
+
+__global__ void k_fill_int(int *p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -232,11 +299,10 @@ int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
                  hipStream_t st) {
   if (batch == 0) return 0;
   if (m == 0) {
-    if (info) {
-      hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * batch, st);
-      return e == hipSuccess ? 0 : (int)e;
-    }
-    return 0;
+    // a fill kernel rather than a memset node, so that the call can be
+    // captured into a graph
+    if (info) hipLaunchKernelGGL(k_fill_int, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch, 0);
+    return info ? launch_status() : 0;
   }
   View A{}, B{};
   if (k > 0) {
@@ -245,10 +311,18 @@ int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
   }
   View C = make_view(sC, ci, cj, m, m);
   View D = make_view(sD, di, dj, m, m);
-  hipLaunchKernelGGL(k_potrf_l, dim3(1, batch), dim3(64 * GW), 0, st, m, k,
-                     A, B, C, D, sD->dA, info,
-                     k > 0 ? batch_stride(sA) : 0, k > 0 ? batch_stride(sB) : 0,
-                     batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  const long long ssA = k > 0 ? batch_stride(sA) : 0, ssB = k > 0 ? batch_stride(sB) : 0;
+  const long long ssC = batch_stride(sC), ssD = batch_stride(sD);
+  const dim3 g(1, batch);
+  switch ((m + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_potrf_reg<1>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 2: hipLaunchKernelGGL(k_potrf_reg<2>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 3: hipLaunchKernelGGL(k_potrf_reg<3>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 4: hipLaunchKernelGGL(k_potrf_reg<4>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    default:
+      hipLaunchKernelGGL(k_potrf_l, g, dim3(64 * GW), 0, st, m, k, A, B, C, D, sD->dA, info,
+                         ssA, ssB, ssC, ssD, ssD);
+  }
   return launch_status();
 }
 

@@ -245,51 +245,6 @@ __device__ __forceinline__ void store_tileT(const View &v, int i0, int j0,
 // "unblocked" LAPACK part is a subroutine on a register-resident block).
 // ---------------------------------------------------------------------------
 
-// Upper Cholesky factorization of a T-tile.  On entry T holds a symmetric
-// block in its upper triangle (rows <= cols); the strictly lower part is
-// ignored.  Rows/cols >= nv are padding and must hold the identity on entry
-// (they stay the identity).  On exit T = U (upper, zero below the diagonal)
-// with U^T U = block, and inv[k] = 1/U[k][k] (LDS, 16 doubles).  Column k is
-// formed from the definition: U[k][k] = sqrt(d_k), U[k][c] = T[k][c]*(1/U[k][k])
-// followed by the rank-1 downdate of the trailing block, for k ascending.
-// `row` is 16 doubles of wave-private LDS.  Returns 0 or k+1 for the first
-// pivot d_k that is not > 0; such a pivot gets inv[k] = 0, which keeps every
-// entry of the earlier rows (columns of L) finite and exact; later entries
-// are unspecified.
-__device__ __forceinline__ int potrf_tile_upper(d4 &T, double *row,
-                                                double *inv) {
-  const int l = lane_id();
-  const int c = l & 15, g = l >> 4;
-  int info = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int rk = k >> 2, gk = k & 3;
-    if (g == gk) row[c] = T[rk];
-    wave_sync();
-    const double d = row[k];
-    const double ukk = sqrt(d);
-    // a failed pivot gets a zero reciprocal: its row of U is zeroed instead
-    // of filled with NaN, so the columns before it stay exact
-    const bool ok = d > 0.0;
-    const double iv = ok ? 1.0 / ukk : 0.0;
-    if (!ok && info == 0) info = k + 1;
-    const double ukc = (c > k) ? row[c] * iv : (c == k ? ukk : 0.0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = g + 4 * r;
-      if (p > k && c > k) T[r] = T[r] - (row[p] * iv) * ukc;
-    }
-    if (g == gk) T[rk] = ukc;
-    if (l == 0) inv[k] = iv;
-    wave_sync();
-  }
-  // zero the strictly lower part
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (g + 4 * r > c) T[r] = 0.0;
-  return info;
-}
-
 // V = U^{-1} for an upper triangular T-tile U with inv[k] = 1/U[k][k]
 // (back substitution, one column per lane group column).  `ulds` is 256
 // doubles of wave-private LDS (U is staged there row-major), `row` is 16.
@@ -363,7 +318,8 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
 //        padding rows/cols >= nv must hold the identity.
 //   Out: T = U (upper, exact zeros below), V = U^{-1} (upper, T-tile),
 //        s.inv[k] = 1/U[k][k].  Returns 0 or k+1 for the first pivot that is
-//        not > 0; that pivot's reciprocal is set to 0 (see potrf_tile_upper).
+//        not > 0; that pivot's reciprocal is set to 0, which keeps every entry of
+//        the earlier rows exact and finite; later entries are unspecified.
 // Pivot k is U[k][k] = sqrt(d_k), U[k][c] = T[k][c]*(1/U[k][k]); at the same
 // time row k of W = L^{-1} = U^{-T} follows from forward substitution,
 //   W[k][c] = (delta_kc - S[k][c]) / U[k][k],  S[p][c] = sum_{q<p} U[q][p] W[q][c].
