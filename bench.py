@@ -229,15 +229,27 @@ def cpu_baseline_uniform(Qh, Bh, Rh, flops_per, min_seconds=10.0):
     done, t0 = 0, time.perf_counter()
     used = threads
     while True:
-        _, _, _, info, used = oracle.batch_syrk_potrf_trsm(Qh, Bh, Rh, nthreads=threads)
+        Lo, Xo, _, info, used = oracle.batch_syrk_potrf_trsm(Qh, Bh, Rh, nthreads=threads)
         done += Qh.shape[0]
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
-    return {"value": round(done * flops_per / el / 1e9, 3), "unit": "GFLOP/s", "cores": int(used),
-            "kind": "oracle",
-            "sample": f"{Qh.shape[0]} instances of the same workload (host copy of the device inputs), "
-                      f"{done // Qh.shape[0]} pass(es), {el:.1f} s, OpenMP over instances"}
+    out = {"value": round(done * flops_per / el / 1e9, 3), "unit": "GFLOP/s", "cores": int(used),
+           "kind": "oracle",
+           "sample": f"{Qh.shape[0]} instances of the same workload (host copy of the device inputs), "
+                     f"{done // Qh.shape[0]} pass(es), {el:.1f} s, OpenMP over instances"}
+    return out, Lo, Xo
+
+
+def parity_vs_oracle(Lg, Xg, Lo, Xo):
+    """Largest relative Frobenius error of the GPU's L (lower) and X over the
+    compared instances, with the 1e-13*n bound of the parity tests."""
+    n = Lg.shape[-1]
+    eL = np.linalg.norm(np.tril(Lg) - Lo, axis=(1, 2)) / np.linalg.norm(Lo, axis=(1, 2))
+    eX = np.linalg.norm(Xg - Xo, axis=(1, 2)) / np.linalg.norm(Xo, axis=(1, 2))
+    worst = float(max(eL.max(), eX.max()))
+    return {"instances": int(Lg.shape[0]), "max_rel_frobenius_err": worst, "bound": 1e-13 * n,
+            "within_bound": bool(worst <= 1e-13 * n)}
 
 
 def main():
@@ -330,8 +342,13 @@ def main():
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         ns = min(B, 16384)
-        cpu = cpu_baseline_uniform(d["Q"][:ns].cpu().numpy(), d["B"][:ns].cpu().numpy(),
-                                   d["RHS"][:ns].cpu().numpy(), fl, args.cpu_seconds)
+        cpu, Lo, Xo = cpu_baseline_uniform(d["Q"][:ns].cpu().numpy(), d["B"][:ns].cpu().numpy(),
+                                           d["RHS"][:ns].cpu().numpy(), fl, args.cpu_seconds)
+        # the oracle's outputs of this leg against the GPU's, first 1024 instances
+        nc = min(1024, ns)
+        Lg = p.unpack_batch(sL).cpu().numpy()[:nc]
+        Xg = p.unpack_batch(sX).cpu().numpy()[:nc]
+        cpu["parity"] = parity_vs_oracle(Lg, Xg, Lo[:nc], Xo[:nc])
 
     out = {
         "metric": "batched dpotrf+dgemm GFLOP/s & % FP64 peak; mixed vs FP64 solves/s @1e-12",

@@ -105,3 +105,20 @@ def test_single_routine_errors_recorded():
     L.blasfeo_dpotrf_l(-1, ctypes.byref(A), 0, 0, ctypes.byref(A), 0, 0)
     assert L.blasfeo_hip_get_last_error() == -1
     assert L.blasfeo_hip_strerror(-5) == b"invalid argument 5"
+
+
+def test_header_compiles_as_c_and_cxx(tmp_path):
+    """The boundary header is plain C: it compiles on its own with a C and a
+    C++ compiler (no HIP or torch types in the signatures)."""
+    import shutil
+    import subprocess
+    inc = os.path.join(ROOT, "include")
+    src = tmp_path / "use.c"
+    src.write_text('#include "blasfeo_hip.h"\nint main(void) { struct blasfeo_dmat m; (void)m; '
+                   'return blasfeo_memsize_dmat(4, 4) > 0 ? 0 : 1; }\n')
+    for cc, std in (("gcc", "-std=c99"), ("g++", "-std=c++17")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, std, "-Wall", "-Werror", "-fsyntax-only", "-I", inc,
+                            "-x", "c" if cc == "gcc" else "c++", str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr

@@ -116,3 +116,12 @@ def test_riccati_full_size_sampled():
     M = d["R"] + np.einsum("bki,bkj->bij", d["B"], d["B"])
     res = np.linalg.norm(Lam @ np.swapaxes(Lam, 1, 2) - M, axis=(1, 2)) / np.linalg.norm(M, axis=(1, 2))
     assert res.max() < 1e-14
+
+
+def test_riccati_bitwise_deterministic():
+    note("riccati determinism")
+    d = synth.riccati_batch(33, seed=7, nx=32, nu=8)
+    F1, i1 = run(d, 5)
+    F2, i2 = run(d, 5)
+    assert np.array_equal(np.nan_to_num(F1, nan=7.0), np.nan_to_num(F2, nan=7.0))
+    assert np.array_equal(i1, i2)

@@ -175,3 +175,21 @@ def test_vbatched_large_kernel_configs(cfg):
         assert list(plan.config()) == [2, 2, 2, 2, cfg, cfg]
         plan.solve(A, L, B, X, info)
         check_all(plan, mats, rhs, L, X, info, nrhs, f"cfg {cfg} nrhs {nrhs}")
+
+
+def test_vbatched_bitwise_deterministic():
+    """Two eager executions of a plan give bit-identical factors and
+    solutions in every size class."""
+    note("vbatched determinism")
+    ns = [3, 16, 30, 48, 64, 100, 180, 250, 320]
+    plan, mats, rhs, A, L, B, X, info = build(ns, 2, seed=12)
+    plan.set_graph(False)
+    plan.solve(A, L, B, X, info)
+    torch.cuda.synchronize()
+    L1, X1 = L.clone(), X.clone()
+    L.fill_(np.nan)
+    X.fill_(np.nan)
+    plan.solve(A, L, B, X, info)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(L, nan=7.0), torch.nan_to_num(L1, nan=7.0))
+    assert torch.equal(torch.nan_to_num(X, nan=7.0), torch.nan_to_num(X1, nan=7.0))
