@@ -92,22 +92,84 @@ __device__ __forceinline__ void st_tile(float *t, const f4 &x) {
   *reinterpret_cast<f4 *>(t + 4 * lane_id()) = x;
 }
 
-// T32 tile of the scaled A(i,j)^T (the U view of block (i,j)):
-// register r of lane (c, g) = s_p s_q a_pq, p = 16i + c, q = 16j + 4g + r;
-// zero outside the matrix and, on diagonal blocks, above the diagonal of A.
-__device__ __forceinline__ f4 load_a32(const View &A, const double *sc, int i,
-                                       int j) {
+// Blocks A(i0 + r, j), r < R, as they enter the U view: element k of lane
+// (c, g) is a_pq with p = 16(i0 + r) + c, q = 16j + 4g + k.  Block rows past
+// the last one repeat it.  Every lane loads unconditionally (masked elements
+// read a_00), so all 4R loads are in flight together.
+template <int R>
+__device__ __forceinline__ void load_a64(const View &A, int i0, int j, int nb,
+                                         double (&v)[R][4]) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
-  f4 t;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = 16 * min(i0 + r, nb - 1) + c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = 16 * j + 4 * g + k;
+      const bool ok = p < A.rows && q < A.rows && p >= q;
+      v[r][k] = A.p[ok ? pm_off(p, q, A.cn) : 0];
+    }
+  }
+}
+
+// acc[r] += fl32(s_p s_q a_pq) on the elements of the lower triangle of A
+// (T32 tiles of the scaled A(i0 + r, j)^T; zero elsewhere)
+template <int R>
+__device__ __forceinline__ void add_a32(const View &A, const double *sc, int i0,
+                                        int j, int nb, const double (&v)[R][4],
+                                        f4 (&acc)[R]) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = 16 * min(i0 + r, nb - 1) + c;
+    const double sp = sc[p];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = 16 * j + 4 * g + k;
+      const bool ok = p < A.rows && q < A.rows && p >= q;
+      const float x = (float)(v[r][k] * sp * sc[q]);
+      acc[r][k] = ok ? acc[r][k] + x : acc[r][k];
+    }
+  }
+}
+
+// T-tile of A(i,j)^T in FP64: register r of lane (c, g) = a_pq with
+// p = 16i + c, q = 16j + g + 4r; zero outside the matrix and, with lower,
+// above the diagonal.  Unconditional loads (masked elements read a_00).
+__device__ __forceinline__ d4 load_a64T(const View &A, int i, int j, bool lower) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int p = 16 * i + c;
+  double v[4];
+  bool ok[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int p = 16 * i + c, q = 16 * j + 4 * g + r;
-    double v = 0.0;
-    if (p < A.rows && q < A.rows && p >= q) v = A.p[pm_off(p, q, A.cn)] * sc[p] * sc[q];
-    t[r] = (float)v;
+    const int q = 16 * j + g + 4 * r;
+    ok[r] = p < A.rows && q < A.rows && (!lower || p >= q);
+    v[r] = A.p[ok[r] ? pm_off(p, q, A.cn) : 0];
   }
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = ok[r] ? v[r] : 0.0;
   return t;
+}
+
+// k-th tile (i, j), i >= j, of step st of the residual sweep: the tiles with
+// i + j = st (mod nb) touch pairwise distinct block rows (k < step_tiles)
+__device__ __forceinline__ int step_tiles(int st, int nb) {
+  return st / 2 + 1 + max(0, (st + nb) / 2 - st);
+}
+__device__ __forceinline__ void step_tile(int st, int nb, int k, int &i, int &j) {
+  const int h = st / 2;
+  if (k <= h) {
+    j = k;
+    i = st - k;
+  } else {
+    j = st + 1 + (k - h - 1);
+    i = st - j + nb;
+  }
 }
 
 // T32 tile (row 4g + r) <-> FP64 T-tile (row g + 4r), through 16x17 doubles
@@ -170,24 +232,42 @@ __device__ __forceinline__ void save_v32(float *buf, const f4 &y, int nrhs) {
   }
 }
 
-// acc -= sum_{q<j} U(q,j)^T U(q,i), two block pairs in flight
-template <bool H>
-__device__ __forceinline__ f4 downdate32(const float *Ut, int j, int i, f4 acc) {
-  int q = 0;
-  for (; q + 2 <= j; q += 2) {
-    const f4 a0 = ld_tile(Ut + 256 * tix_up(q, j));
-    const f4 a1 = ld_tile(Ut + 256 * tix_up(q + 1, j));
-    const f4 b0 = i == j ? a0 : ld_tile(Ut + 256 * tix_up(q, i));
-    const f4 b1 = i == j ? a1 : ld_tile(Ut + 256 * tix_up(q + 1, i));
-    acc = upd_tn<H>(-a0, b0, acc);
-    acc = upd_tn<H>(-a1, b1, acc);
+// acc[r] -= sum_{q<j} U(q,j)^T U(q,i0 + r), r < R: one load of each U(q,j)
+// serves the whole group of R block rows, and the tiles of QU steps of q are
+// loaded together (indices past j - 1 are clamped, their products zeroed).
+// Rows past the last block row repeat the last one (their results are
+// dropped).  With DIAG the group starts at the diagonal block, whose second
+// operand is U(q,j) itself.
+template <bool H, int R, int QU, bool DIAG>
+__device__ __forceinline__ void downdate32_rows(const float *Ut, int j, int i0,
+                                                int nb, f4 (&acc)[R]) {
+  int ti[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = min(i0 + r, nb - 1);
+    ti[r] = i * (i + 1) / 2;
   }
-  if (q < j) {
-    const f4 a0 = ld_tile(Ut + 256 * tix_up(q, j));
-    const f4 b0 = i == j ? a0 : ld_tile(Ut + 256 * tix_up(q, i));
-    acc = upd_tn<H>(-a0, b0, acc);
+  const float *uj = Ut + 256 * (j * (j + 1) / 2);
+  for (int q = 0; q < j; q += QU) {
+    f4 a[QU], b[QU][R];
+#pragma unroll
+    for (int u = 0; u < QU; ++u) {
+      const int qq = min(q + u, j - 1);
+      a[u] = ld_tile(uj + 256 * qq);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (!(DIAG && r == 0)) b[u][r] = ld_tile(Ut + 256 * (ti[r] + qq));
+    }
+#pragma unroll
+    for (int u = 0; u < QU; ++u) {
+      // a skipped step multiplies by zero instead of branching, so that the
+      // compiler keeps its loads with the others
+      const f4 m = (u == 0 || q + u < j) ? -a[u] : zero4f();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        acc[r] = upd_tn<H>(m, (DIAG && r == 0) ? a[u] : b[u][r], acc[r]);
+    }
   }
-  return acc;
 }
 
 // maximum that propagates NaN (a NaN residual must never pass the test)
@@ -220,12 +300,16 @@ struct FacLds {
 };
 
 // Factorization of fl32(S A S) into the workspace tiles, one workgroup of LW
-// waves per instance, left-looking over block columns: wave 0 downdates and
-// factors the diagonal block (FP64 registers, rounded back to FP32), then
-// the waves share the column's off-diagonal blocks.  Little LDS, so that
-// many instances run on a CU at once.  fallback[id] = 1 if a pivot is not
+// waves per instance, left-looking over block columns, block rows in groups
+// of R (one load of the column's tiles per group; a block's entries of
+// fl32(S A S) are added after its downdate sum, so that their loads overlap
+// it): wave 0 takes the group
+// that starts at the diagonal block, factors and inverts that block (FP64
+// registers, rounded back to FP32) and finishes the rest of its group; the
+// waves share the column's remaining groups.  Little LDS, so that many
+// instances run on a CU at once.  fallback[id] = 1 if a pivot is not
 // positive, else 0.
-template <int LW, bool H>
+template <int LW, int R, int QU, bool ZA, bool H>
 __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
   __shared__ FacLds<LW> s;
   const int t = blockIdx.x;
@@ -244,15 +328,24 @@ __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
   float *Vt = Ut + 512LL * nt;
   float *Wt = Vt + 256LL * nb;
   double *tr = s.tr[w];
+  float *trf = reinterpret_cast<float *>(tr);
   double *sc = s.sc;
   for (int p = tid; p < 16 * nb; p += NTH) sc[p] = p < n ? pow2_scale(A.p[pm_off(p, p, cn)]) : 1.0;
   if (tid == 0) s.info = 0;
   __syncthreads();
   // ---------------------------------------------------------------- factor
   for (int j = 0; j < nb; ++j) {
+    f4 Vj = zero4f();
     if (w == 0) {
-      const f4 acc = downdate32<H>(Ut, j, j, load_a32(A, sc, j, j));
-      d4 T = t32_to_t64(acc, tr);
+      double av[R][4];
+      load_a64<R>(A, j, j, nb, av);
+      f4 acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = zero4f();
+      if (!ZA) add_a32<R>(A, sc, j, j, nb, av, acc);
+      downdate32_rows<H, R, QU, true>(Ut, j, j, nb, acc);
+      if (ZA) add_a32<R>(A, sc, j, j, nb, av, acc);
+      d4 T = t32_to_t64(acc[0], tr);
       pad_identity(T, min(16, n - 16 * j));
       d4 V, W;
       const int inf = potrf_inv_tile_upper(T, V, s.diag, &W);
@@ -263,20 +356,43 @@ __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
       st_tile(Ut + 256 * tix_up(j, j), u32);
       st_tile(Vt + 256 * j, v32);
       st_tile(Wt + 256 * j, w32);
-      *reinterpret_cast<f4 *>(s.vsh + 4 * l) = v32;
+      if (LW > 1) *reinterpret_cast<f4 *>(s.vsh + 4 * l) = v32;
+      Vj = v32;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        if (j + r < nb) {
+          const f4 u = mfma32_tn(v32, acc[r], zero4f());
+          st_tile(Ut + 256 * tix_up(j, j + r), u);
+          st_tile(Lt + 256 * tix_up(j, j + r), transpose32(u, trf));
+        }
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
     if (s.info) break;
-    const f4 V = *reinterpret_cast<const f4 *>(s.vsh + 4 * l);
-    for (int i = j + 1 + w; i < nb; i += LW) {
-      const f4 acc = downdate32<H>(Ut, j, i, load_a32(A, sc, i, j));
-      const f4 u = mfma32_tn(V, acc, zero4f());
-      st_tile(Ut + 256 * tix_up(j, i), u);
-      st_tile(Lt + 256 * tix_up(j, i), transpose32(u, reinterpret_cast<float *>(tr)));
+    if (j + R < nb) {
+      const f4 V = w ? *reinterpret_cast<const f4 *>(s.vsh + 4 * l) : Vj;
+      for (int i0 = j + R * (1 + w); i0 < nb; i0 += R * LW) {
+        double av[R][4];
+        load_a64<R>(A, i0, j, nb, av);
+        f4 acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = zero4f();
+        if (!ZA) add_a32<R>(A, sc, i0, j, nb, av, acc);
+        downdate32_rows<H, R, QU, false>(Ut, j, i0, nb, acc);
+        if (ZA) add_a32<R>(A, sc, i0, j, nb, av, acc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (i0 + r < nb) {
+            const f4 u = mfma32_tn(V, acc[r], zero4f());
+            st_tile(Ut + 256 * tix_up(j, i0 + r), u);
+            st_tile(Lt + 256 * tix_up(j, i0 + r), transpose32(u, trf));
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __syncthreads();
   }
   if (tid == 0) {
     a.fallback[id] = s.info ? 1 : 0;
@@ -299,7 +415,7 @@ struct MxLds {
 // FP64 iterative refinement on the factor that k_mx_fac left in the
 // workspace (instances with fallback[id] == 1 are skipped): one workgroup of
 // LW waves per instance, the iterate, residual and solve vectors in LDS.
-template <int LW>
+template <int LW, int RT>
 __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
   extern __shared__ double dyn[];
   __shared__ MxLds<LW> s;
@@ -361,31 +477,54 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
   double worst = 0.0;
   for (;;) {
     // ------------------------------------------------ solve in FP32, in place
+    // block row i is updated by wave i % LW, which also takes its diagonal
+    // step; the inverse of the next diagonal block is loaded a step early
+    // and each wave loads its tiles of a step in groups of RT
+    f4 Dn = w == 0 ? ld_tile(Vt) : zero4f();
     for (int j = 0; j < nb; ++j) {
       if (w == j % LW) {
         const f4 z = load_v32(vz + 16 * j * nr, nr);
-        save_v32(vz + 16 * j * nr, mfma32_tn(ld_tile(Vt + 256 * j), z, zero4f()), nr);
+        save_v32(vz + 16 * j * nr, mfma32_tn(Dn, z, zero4f()), nr);
       }
       __syncthreads();
+      if (j + 1 < nb && w == (j + 1) % LW) Dn = ld_tile(Vt + 256 * (j + 1));
       const f4 y = load_v32(vz + 16 * j * nr, nr);
       const int i0 = j + 1 + ((w - (j + 1) % LW) + LW) % LW;
-      for (int i = i0; i < nb; i += LW) {
-        f4 z = load_v32(vz + 16 * i * nr, nr);
-        z = mfma32_tn(-ld_tile(Ut + 256 * tix_up(j, i)), y, z);
-        save_v32(vz + 16 * i * nr, z, nr);
+      for (int ib = i0; ib < nb; ib += RT * LW) {
+        f4 Us[RT];
+#pragma unroll
+        for (int m = 0; m < RT; ++m) Us[m] = ld_tile(Ut + 256 * tix_up(j, min(ib + m * LW, nb - 1)));
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+          const int i = ib + m * LW;
+          if (i >= nb) break;
+          f4 z = load_v32(vz + 16 * i * nr, nr);
+          z = mfma32_tn(-Us[m], y, z);
+          save_v32(vz + 16 * i * nr, z, nr);
+        }
       }
     }
+    Dn = w == (nb - 1) % LW ? ld_tile(Wt + 256 * (nb - 1)) : zero4f();
     for (int i = nb - 1; i >= 0; --i) {
       if (w == i % LW) {
         const f4 z = load_v32(vz + 16 * i * nr, nr);
-        save_v32(vz + 16 * i * nr, mfma32_tn(ld_tile(Wt + 256 * i), z, zero4f()), nr);
+        save_v32(vz + 16 * i * nr, mfma32_tn(Dn, z, zero4f()), nr);
       }
       __syncthreads();
+      if (i > 0 && w == (i - 1) % LW) Dn = ld_tile(Wt + 256 * (i - 1));
       const f4 xi = load_v32(vz + 16 * i * nr, nr);
-      for (int j = w; j < i; j += LW) {
-        f4 z = load_v32(vz + 16 * j * nr, nr);
-        z = mfma32_tn(-ld_tile(Lt + 256 * tix_up(j, i)), xi, z);
-        save_v32(vz + 16 * j * nr, z, nr);
+      for (int jb = w; jb < i; jb += RT * LW) {
+        f4 Ls[RT];
+#pragma unroll
+        for (int m = 0; m < RT; ++m) Ls[m] = ld_tile(Lt + 256 * tix_up(min(jb + m * LW, i - 1), i));
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+          const int j = jb + m * LW;
+          if (j >= i) break;
+          f4 z = load_v32(vz + 16 * j * nr, nr);
+          z = mfma32_tn(-Ls[m], xi, z);
+          save_v32(vz + 16 * j * nr, z, nr);
+        }
       }
     }
     __syncthreads();
@@ -404,54 +543,65 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
     __syncthreads();
     const bool first = it == 0;
     // step st: the tiles (i, j), i >= j, i + j = st (mod nb) touch distinct
-    // block rows, so their updates of r (and of the row sums) do not collide
+    // block rows, so their updates of r (and of the row sums) do not collide;
+    // each wave loads its tiles of a step in groups of RT before using them
     for (int st = 0; st < nb; ++st) {
-      int k = 0;
-      for (int j = 0; j < nb; ++j) {
-        const int i = (st - j + nb) % nb;
-        if (i < j) continue;
-        if ((k++ % LW) != w) continue;
-        d4 X = load_tileT(A, 16 * i, 16 * j, i == j);  // A(i,j)^T
-        const int c = l & 15, g = l >> 4;
-        d4 ri = load_compact(r64 + 16 * i * nr, nr);
-        ri = mfma_tn(neg4(X), load_compact(x64 + 16 * j * nr, nr), ri);
-        // row sums of |A(i,j)| (rows 16i + c); on a diagonal block, of its
-        // lower part including the diagonal
-        double rs = fabs(X[0]) + fabs(X[1]) + fabs(X[2]) + fabs(X[3]);
-        if (i == j) {  // keep the strictly lower part: it also acts as the upper
+      const int cnt = step_tiles(st, nb);
+      for (int k0 = w; k0 < cnt; k0 += RT * LW) {
+        d4 Xs[RT];
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (c == g + 4 * r) X[r] = 0.0;
+        for (int m = 0; m < RT; ++m) {
+          int i, j;
+          step_tile(st, nb, min(k0 + m * LW, cnt - 1), i, j);
+          Xs[m] = load_a64T(A, i, j, i == j);  // A(i,j)^T
         }
-        if (first) {
-          rs += __shfl_xor(rs, 16);
-          rs += __shfl_xor(rs, 32);
-          if (g == 0) arow[16 * i + c] += rs;
-          // column sums (rows 16j + g + 4r of the symmetric matrix)
-          d4 cs;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double v = fabs(X[r]);
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            cs[r] = v;
-          }
-          if (c == 0) {
+        for (int m = 0; m < RT; ++m) {
+          if (k0 + m * LW >= cnt) break;
+          int i, j;
+          step_tile(st, nb, k0 + m * LW, i, j);
+          d4 X = Xs[m];
+          const int c = l & 15, g = l >> 4;
+          d4 ri = load_compact(r64 + 16 * i * nr, nr);
+          ri = mfma_tn(neg4(X), load_compact(x64 + 16 * j * nr, nr), ri);
+          // row sums of |A(i,j)| (rows 16i + c); on a diagonal block, of its
+          // lower part including the diagonal
+          double rs = fabs(X[0]) + fabs(X[1]) + fabs(X[2]) + fabs(X[3]);
+          if (i == j) {  // keep the strictly lower part: it also acts as the upper
 #pragma unroll
-            for (int r = 0; r < 4; ++r) arow[16 * j + g + 4 * r] += cs[r];
+            for (int r = 0; r < 4; ++r)
+              if (c == g + 4 * r) X[r] = 0.0;
           }
-        }
-        const d4 Xt = transpose_tile(X, tr);  // A(i,j), strictly lower if i == j
-        if (i != j) {
-          save_compact(r64 + 16 * i * nr, ri, nr);
-          d4 rj = load_compact(r64 + 16 * j * nr, nr);
-          rj = mfma_tn(neg4(Xt), load_compact(x64 + 16 * i * nr, nr), rj);
-          save_compact(r64 + 16 * j * nr, rj, nr);
-        } else {
-          ri = mfma_tn(neg4(Xt), load_compact(x64 + 16 * i * nr, nr), ri);
-          save_compact(r64 + 16 * i * nr, ri, nr);
+          if (first) {
+            rs += __shfl_xor(rs, 16);
+            rs += __shfl_xor(rs, 32);
+            if (g == 0) arow[16 * i + c] += rs;
+            // column sums (rows 16j + g + 4r of the symmetric matrix)
+            d4 cs;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              double v = fabs(X[r]);
+              v += __shfl_xor(v, 1);
+              v += __shfl_xor(v, 2);
+              v += __shfl_xor(v, 4);
+              v += __shfl_xor(v, 8);
+              cs[r] = v;
+            }
+            if (c == 0) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) arow[16 * j + g + 4 * r] += cs[r];
+            }
+          }
+          const d4 Xt = transpose_tile(X, tr);  // A(i,j), strictly lower if i == j
+          if (i != j) {
+            save_compact(r64 + 16 * i * nr, ri, nr);
+            d4 rj = load_compact(r64 + 16 * j * nr, nr);
+            rj = mfma_tn(neg4(Xt), load_compact(x64 + 16 * i * nr, nr), rj);
+            save_compact(r64 + 16 * j * nr, rj, nr);
+          } else {
+            ri = mfma_tn(neg4(Xt), load_compact(x64 + 16 * i * nr, nr), ri);
+            save_compact(r64 + 16 * i * nr, ri, nr);
+          }
         }
       }
       __syncthreads();
@@ -529,9 +679,9 @@ size_t mx_lds_bytes(int nbmax, int nrhs) {
   return (size_t)nbmax * 16 * (sizeof(double) * (2 * nrhs + 2) + sizeof(float) * nrhs);
 }
 
-template <int LW>
+template <int LW, int RT>
 static hipError_t mx_prepare(size_t lds) {
-  return hipFuncSetAttribute((const void *)k_mx_ir<LW>,
+  return hipFuncSetAttribute((const void *)k_mx_ir<LW, RT>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -555,7 +705,11 @@ __global__ void k_mx_factor(const float *ws, long long woff, int n, float *dst,
 using namespace bh;
 
 static const int kMxLW = 4;     // waves per instance, refinement
+static const int kMxRT = 4;     // residual tiles per wave loaded together
 static const int kMxFacLW = 1;  // waves per instance, factorization
+static const int kMxFacR = 4;   // block rows per downdate group, factorization
+static const int kMxFacQU = 2;  // steps of the downdate sum loaded together
+static const bool kMxFacZA = true;  // A added after the downdate sum
 
 static int mx_enable(blasfeo_hip_plan *p) {
   if (p->ws) return 0;
@@ -584,7 +738,7 @@ static int mx_enable(blasfeo_hip_plan *p) {
     if (e == hipSuccess)
       e = hipMemcpy(p->d_mx_ids, ids.data(), p->batch * sizeof(int), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = mx_prepare<kMxLW>(lds);
+  if (e == hipSuccess) e = mx_prepare<kMxLW, kMxRT>(lds);
   if (e != hipSuccess) {
     if (p->ws) (void)hipFree(p->ws);
     if (p->d_woff) (void)hipFree(p->d_woff);
@@ -651,10 +805,10 @@ int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
   a.info = info;
   const size_t lds = mx_lds_bytes(p->mx_nbmax, p->nrhs);
   if (prec == 2)
-    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, true>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
+    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, kMxFacR, kMxFacQU, kMxFacZA, true>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
   else
-    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, false>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
-  hipLaunchKernelGGL((k_mx_ir<kMxLW>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
+    hipLaunchKernelGGL((k_mx_fac<kMxFacLW, kMxFacR, kMxFacQU, kMxFacZA, false>), dim3(p->batch), dim3(64 * kMxFacLW), 0, st, a);
+  hipLaunchKernelGGL((k_mx_ir<kMxLW, kMxRT>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
   int e = launch_status();
   if (e) return e;
   // FP64 solve of the instances that fell back
