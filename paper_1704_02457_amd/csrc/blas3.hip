@@ -30,7 +30,7 @@ __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
   B = at_batch(B, sB);
   C = at_batch(C, sC);
   D = at_batch(D, sD);
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
   const int tile = blockIdx.x * GW + w;
   int ti, tj;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
   B = at_batch(B, sB);
   D = at_batch(D, sD);
   __shared__ WaveLds lds[GW];
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int strip = blockIdx.x * GW + w;  // 16 rows of B
   if (strip * 16 >= m) return;
   WaveLds &s = lds[w];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
   const long long b = blockIdx.y;
   double *dAb = dA ? dA + b * sdA : nullptr;
   __shared__ PotrfLds s;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int l = lane_id();
   const int nb = (m + 15) >> 4;
   if (threadIdx.x == 0) s.info = 0;

@@ -35,6 +35,13 @@ __host__ __device__ __forceinline__ long long pm_off(int i, int j, int cn) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+// Index of the wavefront in its workgroup, read from the first lane so that
+// the compiler knows it is uniform: values derived from it (an instance
+// index, a block index used as a buffer offset) stay in scalar registers
+// instead of forcing a loop over lanes around every buffer access.
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
 
 // Orders LDS traffic of one wavefront (no hardware barrier needed: a wave's
 // LDS instructions execute in issue order; this stops compiler reordering).

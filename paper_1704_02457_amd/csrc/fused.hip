@@ -203,7 +203,7 @@ __global__ __launch_bounds__(64 * FW) __attribute__((amdgpu_waves_per_eu(3)))
 void k_syrk_potrf_trsm(FusedArgs a) {
   __shared__ DiagLds lds[FW];
   __shared__ double zl[FW][NB][256];  // right-hand-side blocks, T-tile order
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const long long b = (long long)blockIdx.x * FW + w;
   if (b < a.batch) fused_instance<NB, FULL>(a, b, lds[w], zl[w]);
 }

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
   const int n = a.n[id];
   const int nb = (n + 15) >> 4, cn = (n + 3) & ~3;
   const int nt = nb * (nb + 1) / 2;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int l = lane_id();
   const int tid = threadIdx.x;
   constexpr int NTH = 64 * LW;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
   const int nb = (n + 15) >> 4, cn = (n + 3) & ~3, ld = (n + 15) & ~15;
   const int nt = nb * (nb + 1) / 2;
   const int nr = a.nrhs;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int l = lane_id();
   const int tid = threadIdx.x;
   constexpr int NTH = 64 * LW;

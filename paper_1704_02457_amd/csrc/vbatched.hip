@@ -77,7 +77,7 @@ template <int NB, int VW>
 __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
   __shared__ DiagLds lds[VW];
   __shared__ double zl[VW][NB][256];  // right-hand sides, then y, then x
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int t = blockIdx.x * VW + w;
   if (t >= a.count) return;
   DiagLds &s = lds[w];
@@ -204,21 +204,21 @@ __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
 //   acc -= sum_{q<j} U(q,j)^T U(q,i),  U(q,x) read back from L,
 // UNR block pairs per round so that 2*UNR tile loads are in flight.
 template <int UNR>
-__device__ __forceinline__ d4 downdate(const View &L, int j, int i, d4 acc) {
+__device__ __forceinline__ d4 downdate(const PMat &L, int j, int i, d4 acc) {
   int q = 0;
   for (; q + UNR <= j; q += UNR) {
     d4 uj[UNR], ui[UNR];
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
-      uj[t] = load_tileT(L, 16 * j, 16 * (q + t), false);
-      ui[t] = i == j ? uj[t] : load_tileT(L, 16 * i, 16 * (q + t), false);
+      uj[t] = pm_ldT(L, j, q + t, false);
+      ui[t] = i == j ? uj[t] : pm_ldT(L, i, q + t, false);
     }
 #pragma unroll
     for (int t = 0; t < UNR; ++t) acc = mfma_tn(neg4(uj[t]), ui[t], acc);
   }
   for (; q < j; ++q) {
-    const d4 uj = load_tileT(L, 16 * j, 16 * q, false);
-    const d4 ui = i == j ? uj : load_tileT(L, 16 * i, 16 * q, false);
+    const d4 uj = pm_ldT(L, j, q, false);
+    const d4 ui = i == j ? uj : pm_ldT(L, i, q, false);
     acc = mfma_tn(neg4(uj), ui, acc);
   }
   return acc;
@@ -226,12 +226,12 @@ __device__ __forceinline__ d4 downdate(const View &L, int j, int i, d4 acc) {
 
 // Two block rows i0, i1 of column j at once: each U(q,j) is loaded once for
 // both, and twice as many independent loads are in flight per step.
-__device__ __forceinline__ void downdate_pair(const View &L, int j, int i0, int i1,
+__device__ __forceinline__ void downdate_pair(const PMat &L, int j, int i0, int i1,
                                               d4 &acc0, d4 &acc1) {
   for (int q = 0; q < j; ++q) {
-    const d4 uj = load_tileT(L, 16 * j, 16 * q, false);
-    const d4 ua = load_tileT(L, 16 * i0, 16 * q, false);
-    const d4 ub = load_tileT(L, 16 * i1, 16 * q, false);
+    const d4 uj = pm_ldT(L, j, q, false);
+    const d4 ua = pm_ldT(L, i0, q, false);
+    const d4 ub = pm_ldT(L, i1, q, false);
     acc0 = mfma_tn(neg4(uj), ua, acc0);
     acc1 = mfma_tn(neg4(uj), ub, acc1);
   }
@@ -240,14 +240,14 @@ __device__ __forceinline__ void downdate_pair(const View &L, int j, int i0, int 
 // Gemm downdate as above with the U(q,j) tiles of the column staged in LDS
 // (ul, one 16x16 T-tile per 256 doubles): one global tile load per update.
 template <int DU>
-__device__ __forceinline__ d4 downdate_staged(const double *ul, const View &L, int j,
+__device__ __forceinline__ d4 downdate_staged(const double *ul, const PMat &L, int j,
                                               int i, d4 acc) {
   const int l = lane_id();
   int q = 0;
   for (; q + DU <= j; q += DU) {
     d4 ui[DU];
 #pragma unroll
-    for (int e = 0; e < DU; ++e) ui[e] = load_tileT(L, 16 * i, 16 * (q + e), false);
+    for (int e = 0; e < DU; ++e) ui[e] = pm_ldT(L, i, q + e, false);
 #pragma unroll
     for (int e = 0; e < DU; ++e) {
       d4 uj;
@@ -260,7 +260,7 @@ __device__ __forceinline__ d4 downdate_staged(const double *ul, const View &L, i
     d4 uj;
 #pragma unroll
     for (int r = 0; r < 4; ++r) uj[r] = ul[q * 256 + 64 * r + l];
-    acc = mfma_tn(neg4(uj), load_tileT(L, 16 * i, 16 * q, false), acc);
+    acc = mfma_tn(neg4(uj), pm_ldT(L, i, q, false), acc);
   }
   return acc;
 }
@@ -290,11 +290,11 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
   const int n = a.n[id];
   const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
   const int nb = pm;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int l = lane_id();
-  View A{const_cast<double *>(a.A + a.moff[id]), cn, 0, 0, n, n};
-  View L{a.L + a.moff[id], cn, 0, 0, n, n};
-  double *dAb = L.p + (long long)pm * 16 * cn;
+  const PMat A = make_pmat(a.A + a.moff[id], n, cn);
+  const PMat L = make_pmat(a.L + a.moff[id], n, cn);
+  double *dAb = a.L + a.moff[id] + (long long)pm * 16 * cn;
   const bool has_rhs = a.nrhs > 0;
   const double *Bb = has_rhs ? a.B + a.voff[id] : nullptr;
   double *wl = a.wsw + a.wwoff[id];
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     const int nv = min(16, n - 16 * j);
     if constexpr (ST) {
       for (int q = w; q < j; q += LW) {
-        const d4 u = load_tileT(L, 16 * j, 16 * q, false);
+        const d4 u = pm_ldT(L, j, q, false);
 #pragma unroll
         for (int r = 0; r < 4; ++r) ul[q * 256 + 64 * r + l] = u[r];
       }
@@ -317,12 +317,12 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
         for (int r = 0; r < 4; ++r) u[r] = ul[q * 256 + 64 * r + l];
         return u;
       } else {
-        return load_tileT(L, 16 * j, 16 * q, false);
+        return pm_ldT(L, j, q, false);
       }
     };
     if (w == 0) {
       // diagonal downdate and forward substitution, one load of U(q,j) each
-      d4 t0 = load_tileT(A, 16 * j, 16 * j, true);
+      d4 t0 = pm_ldT(A, j, j, true);
       d4 z = has_rhs ? load_rhs(Bb, ld, n, a.nrhs, j) : zero4();
       int q = 0;
       if constexpr (!ST) {
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
       d4 V, W;
       const int inf = potrf_inv_tile_upper(t0, V, s, &W);
       if (inf && l == 0 && sinfo == 0) sinfo = 16 * j + inf;
-      store_tileT(L, 16 * j, 16 * j, t0, true);
+      pm_stT(L, j, j, t0, true);
       if (l < nv) dAb[16 * j + l] = s.inv[l];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -364,21 +364,21 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     int i = j + 1 + w;
     if constexpr (!ST && PAIR) {
       for (; i + LW < nb; i += 2 * LW) {
-        d4 t0 = load_tileT(A, 16 * i, 16 * j, false);
-        d4 t1 = load_tileT(A, 16 * (i + LW), 16 * j, false);
+        d4 t0 = pm_ldT(A, i, j, false);
+        d4 t1 = pm_ldT(A, i + LW, j, false);
         downdate_pair(L, j, i, i + LW, t0, t1);
-        store_tileT(L, 16 * i, 16 * j, mfma_tn(V, t0, zero4()), false);
-        store_tileT(L, 16 * (i + LW), 16 * j, mfma_tn(V, t1, zero4()), false);
+        pm_stT(L, i, j, mfma_tn(V, t0, zero4()), false);
+        pm_stT(L, i + LW, j, mfma_tn(V, t1, zero4()), false);
       }
     }
     for (; i < nb; i += LW) {
-      const d4 a0 = load_tileT(A, 16 * i, 16 * j, false);
+      const d4 a0 = pm_ldT(A, i, j, false);
       d4 t1;
       if constexpr (ST)
         t1 = downdate_staged<DU>(ul, L, j, i, a0);
       else
         t1 = downdate<DU>(L, j, i, a0);
-      store_tileT(L, 16 * i, 16 * j, mfma_tn(V, t1, zero4()), false);
+      pm_stT(L, i, j, mfma_tn(V, t1, zero4()), false);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     for (int j = nb - 1; j >= 0; --j) {
       d4 acc = load_compact(yl + (long long)j * 16 * nr, nr);
       for (int i = j + 1; i < nb; ++i) {
-        const d4 ut = load_tileN(L, 16 * i, 16 * j);  // L(i,j) = U(j,i)^T
+        const d4 ut = pm_ldN(L, i, j);  // L(i,j) = U(j,i)^T
         acc = mfma_tn(neg4(ut), load_compact(yl + (long long)i * 16 * nr, nr), acc);
       }
       d4 W;
