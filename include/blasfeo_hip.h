@@ -338,7 +338,9 @@ int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
  * 64): wavefronts per workgroup, 1, 2 or 4.  Classes 4 (192 < n <= 512)
  * and 5 (64 < n <= 192): waves per instance, 1, 2, 4, 8 or 16, plus 100 for
  * the variant that stages each block column of the factor in LDS (104, 108,
- * 116). */
+ * 116), plus 200 for the variant that factors two block columns per step
+ * with one block row per downdate group of a wave (201, 202, 204), plus 210
+ * for the same with two block rows per group (211, 212, 214). */
 int blasfeo_hip_plan_config(const blasfeo_hip_plan *plan, int *cfg_out);
 /* Sets the configuration of every size class (count = the number of
  * classes; values as above); drops the captured graph.  Returns 0, -2 for

@@ -197,6 +197,15 @@ __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
 
 // ---------------------------------------------------------------- n > 64
 
+// off-diagonal blocks of a column: block rows per downdate group of a wave,
+// and steps of the downdate sum loaded together
+constexpr int kVbGroupRows = 2;
+constexpr int kVbGroupSteps = 1;
+// back substitution: tiles loaded together
+constexpr int kVbBackSteps = 1;
+// diagonal downdate: steps loaded together
+constexpr int kVbDiagSteps = 2;
+
 // Dynamic LDS of k_vb_large: W_j tiles (nbmax x 256), compact y/x blocks
 // (nbmax x 16 x nrhs), the current V (256), diagonal scratch.
 
@@ -234,6 +243,35 @@ __device__ __forceinline__ void downdate_pair(const PMat &L, int j, int i0, int 
     const d4 ub = pm_ldT(L, i1, q, false);
     acc0 = mfma_tn(neg4(uj), ua, acc0);
     acc1 = mfma_tn(neg4(uj), ub, acc1);
+  }
+}
+
+// R block rows i0 + r * stride (r < R) of column j at once: one load of
+// each U(q,j) serves the whole group, and the tiles of QU steps of q are
+// loaded together (steps past j - 1 reload the last one and are multiplied
+// by zero; rows past the last block row repeat it and their results are
+// dropped by the caller).
+template <int R, int QU>
+__device__ __forceinline__ void downdate_rows(const PMat &L, int j, int i0,
+                                              int stride, int nb, d4 (&acc)[R]) {
+  int ir[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ir[r] = min(i0 + r * stride, nb - 1);
+  for (int q = 0; q < j; q += QU) {
+    d4 uj[QU], ui[QU][R];
+#pragma unroll
+    for (int u = 0; u < QU; ++u) {
+      const int qq = min(q + u, j - 1);
+      uj[u] = pm_ldT(L, j, qq, false);
+#pragma unroll
+      for (int r = 0; r < R; ++r) ui[u][r] = pm_ldT(L, ir[r], qq, false);
+    }
+#pragma unroll
+    for (int u = 0; u < QU; ++u) {
+      const d4 m = (u == 0 || q + u < j) ? neg4(uj[u]) : zero4();
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = mfma_tn(m, ui[u][r], acc[r]);
+    }
   }
 }
 
@@ -275,7 +313,8 @@ __device__ __forceinline__ d4 downdate_staged(const double *ul, const PMat &L, i
 // mostly miss the L2, are halved.
 template <int LW, bool ST, bool PAIR = true>
 __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) void k_vb_large(VbArgs a, int nbmax) {
-  constexpr int DU = ST ? 4 : 2;
+  constexpr int DU = ST ? 4 : kVbDiagSteps;
+  constexpr int GR = kVbGroupRows, GQ = kVbGroupSteps, BQ = kVbBackSteps;
   extern __shared__ double dyn[];
   __shared__ DiagLds s;
   __shared__ double vsh[256];
@@ -363,12 +402,22 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     for (int r = 0; r < 4; ++r) V[r] = vsh[64 * r + l];
     int i = j + 1 + w;
     if constexpr (!ST && PAIR) {
-      for (; i + LW < nb; i += 2 * LW) {
-        d4 t0 = pm_ldT(A, i, j, false);
-        d4 t1 = pm_ldT(A, i + LW, j, false);
-        downdate_pair(L, j, i, i + LW, t0, t1);
-        pm_stT(L, i, j, mfma_tn(V, t0, zero4()), false);
-        pm_stT(L, i + LW, j, mfma_tn(V, t1, zero4()), false);
+      // groups of GR rows of this wave; the blocks of A are added after the
+      // downdate sum so that their loads overlap it
+      for (; i < nb; i += GR * LW) {
+        d4 av[GR], acc[GR];
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+          av[r] = pm_ldT(A, min(i + r * LW, nb - 1), j, false);
+          acc[r] = zero4();
+        }
+        downdate_rows<GR, GQ>(L, j, i, LW, nb, acc);
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+          if (i + r * LW < nb) {
+            pm_stT(L, i + r * LW, j, mfma_tn(V, av[r] + acc[r], zero4()), false);
+          }
+        }
       }
     }
     for (; i < nb; i += LW) {
@@ -382,6 +431,191 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
+  }
+  if (has_rhs && w == 0) {
+    double *Xb = a.X + a.voff[id];
+    for (int j = nb - 1; j >= 0; --j) {
+      d4 acc = load_compact(yl + (long long)j * 16 * nr, nr);
+      // BQ tiles L(i,j) = U(j,i)^T in flight at a time (indices past the
+      // last block row reload it and are multiplied by zero)
+      for (int i = j + 1; i < nb; i += BQ) {
+        d4 ut[BQ];
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) ut[u] = pm_ldN(L, min(i + u, nb - 1), j);
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const d4 m = (u == 0 || i + u < nb) ? neg4(ut[u]) : zero4();
+          acc = mfma_tn(m, load_compact(yl + (long long)min(i + u, nb - 1) * 16 * nr, nr), acc);
+        }
+      }
+      d4 W;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[r] = wl[(long long)j * 256 + 64 * r + l];
+      const d4 x = mfma_tn(W, acc, zero4());
+      save_compact(yl + (long long)j * 16 * nr, x, nr);
+      store_rhs(Xb, ld, n, a.nrhs, j, x);
+    }
+  }
+  if (a.info && threadIdx.x == 0) a.info[id] = sinfo;
+}
+
+// Two block columns j, j+1 at once: acc0[r] -= sum_{q<j} U(q,j)^T U(q,i_r)
+// and acc1[r] -= sum_{q<j} U(q,j+1)^T U(q,i_r) for the R rows
+// i_r = i0 + r * stride (rows past the last block row repeat it); each
+// U(q,i_r) is loaded once for both columns and each U(q,j), U(q,j+1) once
+// for all R rows: 2 + R tile loads per 2R products.
+template <int R>
+__device__ __forceinline__ void downdate_cols2(const PMat &L, int j, int i0,
+                                               int stride, int nb, d4 (&acc0)[R],
+                                               d4 (&acc1)[R]) {
+  int ir[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ir[r] = min(i0 + r * stride, nb - 1);
+  for (int q = 0; q < j; ++q) {
+    const d4 u0 = pm_ldT(L, j, q, false), u1 = pm_ldT(L, j + 1, q, false);
+    d4 ui[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ui[r] = pm_ldT(L, ir[r], q, false);
+    const d4 m0 = neg4(u0), m1 = neg4(u1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      acc0[r] = mfma_tn(m0, ui[r], acc0[r]);
+      acc1[r] = mfma_tn(m1, ui[r], acc1[r]);
+    }
+  }
+}
+
+// Left-looking over pairs of block columns (the blocked form of §4.6 with a
+// panel two blocks wide), one workgroup of LW waves per instance.  Wave 0
+// downdates the 2x2 diagonal blocks and the two right-hand-side blocks with
+// one load of U(q,j), U(q,j+1) per step, factors block j, forms U(j,j+1),
+// downdates and factors block j+1; then the waves share the remaining block
+// rows, each row's left part read once for both columns.  Against the
+// one-column kernel this halves the serial diagonal steps and barriers, and
+// with R = 2 rows per group cuts the re-reads of the factor's left part by a
+// third.  Same outputs and workspace use.
+template <int LW, int R>
+__global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) void k_vb_large_cp(VbArgs a, int nbmax) {
+  extern __shared__ double dyn[];
+  __shared__ DiagLds s;
+  __shared__ double vsh[3][256];  // V_j, V_{j+1}, U(j,j+1)
+  __shared__ int sinfo;
+  const int nr = a.nrhs > 0 ? a.nrhs : 1;
+  double *yl = dyn;  // nbmax * 16 * nr
+  const int t = blockIdx.x;
+  if (t >= a.count) return;
+  const int id = a.ids[t];
+  if (a.only && a.only[id] == 0) return;
+  const int n = a.n[id];
+  const int cn = cn_of(n), ld = ld_of(n), pm = (n + 15) >> 4;
+  const int nb = pm;
+  const int w = wave_id();
+  const int l = lane_id();
+  const PMat A = make_pmat(a.A + a.moff[id], n, cn);
+  const PMat L = make_pmat(a.L + a.moff[id], n, cn);
+  double *dAb = a.L + a.moff[id] + (long long)pm * 16 * cn;
+  const bool has_rhs = a.nrhs > 0;
+  const double *Bb = has_rhs ? a.B + a.voff[id] : nullptr;
+  double *wl = a.wsw + a.wwoff[id];
+  if (threadIdx.x == 0) sinfo = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; j += 2) {
+    const bool two = j + 1 < nb;
+    const int jb = two ? j + 1 : j;
+    if (w == 0) {
+      d4 t00 = pm_ldT(A, j, j, true);
+      d4 t01 = pm_ldT(A, jb, j, false);
+      d4 t11 = pm_ldT(A, jb, jb, true);
+      d4 z0 = has_rhs ? load_rhs(Bb, ld, n, a.nrhs, j) : zero4();
+      d4 z1 = has_rhs ? load_rhs(Bb, ld, n, a.nrhs, jb) : zero4();
+      for (int q = 0; q < j; ++q) {
+        const d4 u0 = pm_ldT(L, j, q, false), u1 = pm_ldT(L, jb, q, false);
+        const d4 m0 = neg4(u0), m1 = neg4(u1);
+        t00 = mfma_tn(m0, u0, t00);
+        t01 = mfma_tn(m0, u1, t01);
+        t11 = mfma_tn(m1, u1, t11);
+        if (has_rhs) {
+          const d4 y = load_compact(yl + (long long)q * 16 * nr, nr);
+          z0 = mfma_tn(m0, y, z0);
+          z1 = mfma_tn(m1, y, z1);
+        }
+      }
+      // block j
+      pad_identity(t00, min(16, n - 16 * j));
+      d4 V0, W0;
+      int inf = potrf_inv_tile_upper(t00, V0, s, &W0);
+      if (inf && l == 0 && sinfo == 0) sinfo = 16 * j + inf;
+      pm_stT(L, j, j, t00, true);
+      if (l < min(16, n - 16 * j)) dAb[16 * j + l] = s.inv[l];
+      const d4 y0 = mfma_tn(V0, z0, zero4());
+      if (has_rhs) save_compact(yl + (long long)j * 16 * nr, y0, nr);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        wl[(long long)j * 256 + 64 * r + l] = W0[r];
+        vsh[0][64 * r + l] = V0[r];
+      }
+      if (two) {
+        // U(j,j+1), then block j+1
+        const d4 u01 = mfma_tn(V0, t01, zero4());
+        pm_stT(L, j + 1, j, u01, false);
+        t11 = mfma_tn(neg4(u01), u01, t11);
+        z1 = mfma_tn(neg4(u01), y0, z1);
+        const int nv1 = min(16, n - 16 * (j + 1));
+        pad_identity(t11, nv1);
+        d4 V1, W1;
+        inf = potrf_inv_tile_upper(t11, V1, s, &W1);
+        if (inf && l == 0 && sinfo == 0) sinfo = 16 * (j + 1) + inf;
+        pm_stT(L, j + 1, j + 1, t11, true);
+        if (l < nv1) dAb[16 * (j + 1) + l] = s.inv[l];
+        if (has_rhs) save_compact(yl + (long long)(j + 1) * 16 * nr, mfma_tn(V1, z1, zero4()), nr);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          wl[(long long)(j + 1) * 256 + 64 * r + l] = W1[r];
+          vsh[1][64 * r + l] = V1[r];
+          vsh[2][64 * r + l] = u01[r];
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    if (two && j + 2 < nb) {
+      d4 V0, V1, U01;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        V0[r] = vsh[0][64 * r + l];
+        V1[r] = vsh[1][64 * r + l];
+        U01[r] = vsh[2][64 * r + l];
+      }
+      const d4 mU01 = neg4(U01);
+      for (int i = j + 2 + w; i < nb; i += R * LW) {
+        d4 acc0[R], acc1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc0[r] = zero4();
+          acc1[r] = zero4();
+        }
+        downdate_cols2<R>(L, j, i, LW, nb, acc0, acc1);
+        d4 a0[R], a1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int ii = min(i + r * LW, nb - 1);
+          a0[r] = pm_ldT(A, ii, j, false);
+          a1[r] = pm_ldT(A, ii, j + 1, false);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int ii = i + r * LW;
+          if (ii < nb) {
+            const d4 uji = mfma_tn(V0, a0[r] + acc0[r], zero4());
+            pm_stT(L, ii, j, uji, false);
+            const d4 t1 = mfma_tn(mU01, uji, a1[r] + acc1[r]);
+            pm_stT(L, ii, j + 1, mfma_tn(V1, t1, zero4()), false);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
+    }
   }
   if (has_rhs && w == 0) {
     double *Xb = a.X + a.voff[id];
@@ -459,11 +693,23 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
     case 3: launch_small<3>(a, bk.cfg, st); break;
     case 4: launch_small<4>(a, bk.cfg, st); break;
     default: {
-      const bool staged = bk.cfg >= 100;
+      const bool pair = bk.cfg >= 200;
+      const bool staged = !pair && bk.cfg >= 100;
       const int lw = bk.cfg % 100;
       const size_t lds = large_lds_bytes(bk.nbmax, p->nrhs, staged);
       const dim3 g(bk.count), b(64 * lw);
-      if (staged) {
+      if (pair) {
+        const int lwp = bk.cfg % 10;
+        if (bk.cfg >= 210) {
+          if (lwp == 4) hipLaunchKernelGGL((k_vb_large_cp<4, 2>), g, dim3(256), lds, st, a, bk.nbmax);
+          else if (lwp == 2) hipLaunchKernelGGL((k_vb_large_cp<2, 2>), g, dim3(128), lds, st, a, bk.nbmax);
+          else hipLaunchKernelGGL((k_vb_large_cp<1, 2>), g, dim3(64), lds, st, a, bk.nbmax);
+        } else {
+          if (lwp == 4) hipLaunchKernelGGL((k_vb_large_cp<4, 1>), g, dim3(256), lds, st, a, bk.nbmax);
+          else if (lwp == 2) hipLaunchKernelGGL((k_vb_large_cp<2, 1>), g, dim3(128), lds, st, a, bk.nbmax);
+          else hipLaunchKernelGGL((k_vb_large_cp<1, 1>), g, dim3(64), lds, st, a, bk.nbmax);
+        }
+      } else if (staged) {
         if (lw == 16) hipLaunchKernelGGL((k_vb_large<16, true>), g, b, lds, st, a, bk.nbmax);
         else if (lw == 8) hipLaunchKernelGGL((k_vb_large<8, true>), g, b, lds, st, a, bk.nbmax);
         else hipLaunchKernelGGL((k_vb_large<4, true>), g, b, lds, st, a, bk.nbmax);
@@ -581,6 +827,12 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
     for (int k = 0; k < 8 && e == hipSuccess; ++k)
       e = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)large_lds_bytes(nbm, nrhs, k < 3));
+    const void *kp[6] = {(const void *)k_vb_large_cp<1, 1>, (const void *)k_vb_large_cp<2, 1>,
+                         (const void *)k_vb_large_cp<4, 1>, (const void *)k_vb_large_cp<1, 2>,
+                         (const void *)k_vb_large_cp<2, 2>, (const void *)k_vb_large_cp<4, 2>};
+    for (int k = 0; k < 6 && e == hipSuccess; ++k)
+      e = hipFuncSetAttribute(kp[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)large_lds_bytes(nbm, nrhs, false));
   }
   if (e != hipSuccess) {
     blasfeo_hip_plan_destroy(p);
@@ -611,7 +863,8 @@ int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *p, int on) {
 static bool cfg_valid(int kind, int cfg) {
   if (kind) return cfg == 1 || cfg == 2 || cfg == 4;
   return cfg == 1 || cfg == 2 || cfg == 4 || cfg == 8 || cfg == 16 || cfg == 104 ||
-         cfg == 108 || cfg == 116;
+         cfg == 108 || cfg == 116 || cfg == 201 || cfg == 202 || cfg == 204 ||
+         cfg == 211 || cfg == 212 || cfg == 214;
 }
 
 int blasfeo_hip_plan_set_config(blasfeo_hip_plan *p, const int *cfg, int count) {
@@ -691,9 +944,9 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
   for (auto &bk : p->buckets) {
     if (bk.count == 0) continue;
     const int cands_small[3] = {1, 2, 4};
-    const int cands_large[6] = {1, 2, 4, 8, 104, 108};
+    const int cands_large[11] = {1, 2, 4, 8, 104, 108, 201, 202, 204, 211, 212};
     const int *cands = bk.kind ? cands_small : cands_large;
-    const int nc = bk.kind ? 3 : 6;
+    const int nc = bk.kind ? 3 : 11;
     float best = 1e30f;
     int best_cfg = bk.cfg;
     for (int ci = 0; ci < nc && !err; ++ci) {

@@ -120,6 +120,34 @@ def test_vbatched_failure_is_per_instance():
     assert [inf[i] for i in bad] == [col + 1 for col in bad.values()]
 
 
+@pytest.mark.parametrize("cfg", [2, 201, 202, 204, 211, 212])
+def test_vbatched_failure_large_configs(cfg):
+    """A non-positive pivot in the first or the second block column of a
+    column pair, or in a trailing single block column, is reported at its
+    1-based position; the other instances are unaffected."""
+    note("vbatched large failure cfg", cfg)
+    ns = [100, 150, 150, 129, 200]
+    plan, mats, rhs, A, L, B, X, info = build(ns, 2, seed=20 + cfg)
+    bad = {0: 20, 1: 70, 2: 90, 3: 128}
+    for i, col in bad.items():
+        M = mats[i].copy()
+        M[col, col] = -1.0
+        mats[i] = M
+        p.pack(torch.as_tensor(M, device=DEV), out=plan.dmat(A, i))
+    plan.set_config([2, 2, 2, 2, cfg, cfg])
+    plan.solve(A, L, B, X, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    for i, n in enumerate(ns):
+        Lr, _, ir = oracle.dpotrf_l(mats[i])
+        assert inf[i] == ir, (cfg, i, inf[i], ir)
+        if ir == 0:
+            Lg = p.unpack(plan.dmat(L, i)).cpu().numpy()
+            assert_parity(np.tril(Lg), Lr, n, f"L {i}")
+            assert_parity(plan.rhs(X, i).cpu().numpy(), oracle.dpotrs_l(Lr, rhs[i]), n, f"X {i}")
+    assert [inf[i] for i in bad] == [col + 1 for col in bad.values()]
+
+
 def test_vbatched_full_size_sampled():
     """The uneven workload at full size (65536 systems, n = 8*U{1..32}, one
     right-hand side) in the benchmark's configuration; 64 sampled systems
@@ -163,7 +191,7 @@ def test_vbatched_full_size_sampled():
     del rng
 
 
-@pytest.mark.parametrize("cfg", [4, 8, 16, 104, 108, 116])
+@pytest.mark.parametrize("cfg", [4, 8, 16, 104, 108, 116, 201, 202, 204, 211, 212, 214])
 def test_vbatched_large_kernel_configs(cfg):
     """Every launch configuration of the n > 64 class, with and without
     right-hand sides, ragged orders up to the largest supported one."""
