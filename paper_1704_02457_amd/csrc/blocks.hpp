@@ -173,15 +173,21 @@ struct View {
   int rows, cols;  // extent of the sub-matrix
 };
 
+// The loads below are unconditional: an element outside the sub-matrix is
+// read from the sub-matrix origin and replaced by zero, so that the loads of
+// a tile are all in flight at once (a load under a branch is waited for
+// inside the branch).  The sub-matrix must therefore be non-empty, which
+// every caller guarantees by only addressing blocks that exist.
+
 // A/B operand fragment of the 16x4 block X = S[i0:i0+16, k0:k0+4] of the
 // sub-matrix S: lane l holds X[l & 15][l >> 4] (zero outside S).  Used as
 // the A operand it supplies X; used as the B operand it supplies X^T.
 __device__ __forceinline__ double load_frag(const View &v, int i0, int k0) {
   const int l = lane_id();
   const int i = i0 + (l & 15), k = k0 + (l >> 4);
-  double x = 0.0;
-  if (i < v.rows && k < v.cols) x = v.p[pm_off(v.ai + i, v.aj + k, v.cn)];
-  return x;
+  const bool ok = i < v.rows && k < v.cols;
+  const double x = v.p[ok ? pm_off(v.ai + i, v.aj + k, v.cn) : pm_off(v.ai, v.aj, v.cn)];
+  return ok ? x : 0.0;
 }
 
 // T-tile holding the transpose of the block S[i0:i0+16, j0:j0+16]:
@@ -191,15 +197,18 @@ __device__ __forceinline__ d4 load_tileT(const View &v, int i0, int j0,
                                          bool lower_only) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
-  d4 t;
+  const int o0 = pm_off(v.ai, v.aj, v.cn);
+  double x[4];
+  bool ok[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + c, j = j0 + g + 4 * r;
-    double x = 0.0;
-    if (i < v.rows && j < v.cols && (!lower_only || i >= j))
-      x = v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
-    t[r] = x;
+    ok[r] = i < v.rows && j < v.cols && (!lower_only || i >= j);
+    x[r] = v.p[ok[r] ? pm_off(v.ai + i, v.aj + j, v.cn) : o0];
   }
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = ok[r] ? x[r] : 0.0;
   return t;
 }
 
@@ -208,14 +217,18 @@ __device__ __forceinline__ d4 load_tileT(const View &v, int i0, int j0,
 __device__ __forceinline__ d4 load_tileN(const View &v, int i0, int j0) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
-  d4 t;
+  const int o0 = pm_off(v.ai, v.aj, v.cn);
+  double x[4];
+  bool ok[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + g + 4 * r, j = j0 + c;
-    double x = 0.0;
-    if (i < v.rows && j < v.cols) x = v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
-    t[r] = x;
+    ok[r] = i < v.rows && j < v.cols;
+    x[r] = v.p[ok[r] ? pm_off(v.ai + i, v.aj + j, v.cn) : o0];
   }
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = ok[r] ? x[r] : 0.0;
   return t;
 }
 

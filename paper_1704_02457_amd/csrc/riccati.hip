@@ -38,7 +38,7 @@ __device__ __forceinline__ int unpad(int x, int nu) {
 }
 
 template <int NUB, int NXB>
-__global__ __launch_bounds__(64) void k_ric_trf(RicArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ric_trf(RicArgs a) {
   constexpr int NB = NUB + NXB;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int NLT = NXB * (NXB + 1) / 2;
