@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="time only the uniform-batch workload")
+    ap.add_argument("--legs", default="uneven,riccati,mixed",
+                    help="comma list of the further workloads to time (uneven, riccati, mixed)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -323,11 +325,14 @@ def main():
         "uniform_failed_instances": bad,
     }
 
-    if not args.no_extra:
+    legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
+    if "uneven" in legs:
         print("[bench] uneven batch (65536 solves)", file=sys.stderr, flush=True)
         extra.update(bench_uneven(p, synth, torch))
+    if "riccati" in legs:
         print("[bench] Riccati batch (4096 x N=20)", file=sys.stderr, flush=True)
         extra.update(bench_riccati(p, synth, torch))
+    if "mixed" in legs:
         print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
         extra.update(bench_mixed(p, synth, torch))
 
