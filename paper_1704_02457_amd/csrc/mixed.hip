@@ -156,6 +156,28 @@ __device__ __forceinline__ d4 load_a64T(const View &A, int i, int j, bool lower)
   return t;
 }
 
+// T-tile of A(i,j) itself in FP64: register r of lane (c, g) = a_pq with
+// p = 16i + g + 4r, q = 16j + c; zero outside the matrix and, with strict,
+// on and above the diagonal.  Unconditional loads (masked elements read
+// a_00).
+__device__ __forceinline__ d4 load_a64N(const View &A, int i, int j, bool strict) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int q = 16 * j + c;
+  double v[4];
+  bool ok[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int p = 16 * i + g + 4 * r;
+    ok[r] = p < A.rows && q < A.rows && (!strict || p > q);
+    v[r] = A.p[ok[r] ? pm_off(p, q, A.cn) : 0];
+  }
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = ok[r] ? v[r] : 0.0;
+  return t;
+}
+
 // k-th tile (i, j), i >= j, of step st of the residual sweep: the tiles with
 // i + j = st (mod nb) touch pairwise distinct block rows (k < step_tiles)
 __device__ __forceinline__ int step_tiles(int st, int nb) {
@@ -406,7 +428,6 @@ __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
 
 template <int LW>
 struct MxLds {
-  double tr[LW][16 * 17];       // per wave: transposes
   double eprev[16];             // backward error per right-hand side
   double rmax[16], xmax[16], bmax[16];
   double anorm;
@@ -447,8 +468,6 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
   float *Lt = Ut + 256LL * nt;
   float *Vt = Ut + 512LL * nt;
   float *Wt = Vt + 256LL * nb;
-  double *tr = s.tr[w];
-
   for (int p = tid; p < nv16; p += NTH) {
     sc[p] = p < n ? pow2_scale(A.p[pm_off(p, p, cn)]) : 1.0;
     arow[p] = 0.0;
@@ -548,12 +567,13 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
     for (int st = 0; st < nb; ++st) {
       const int cnt = step_tiles(st, nb);
       for (int k0 = w; k0 < cnt; k0 += RT * LW) {
-        d4 Xs[RT];
+        d4 Xs[RT], Ns[RT];
 #pragma unroll
         for (int m = 0; m < RT; ++m) {
           int i, j;
           step_tile(st, nb, min(k0 + m * LW, cnt - 1), i, j);
           Xs[m] = load_a64T(A, i, j, i == j);  // A(i,j)^T
+          Ns[m] = load_a64N(A, i, j, i == j);  // A(i,j), strictly lower if i == j
         }
 #pragma unroll
         for (int m = 0; m < RT; ++m) {
@@ -592,7 +612,7 @@ __global__ __launch_bounds__(64 * LW) void k_mx_ir(MxArgs a, int nbmax) {
               for (int r = 0; r < 4; ++r) arow[16 * j + g + 4 * r] += cs[r];
             }
           }
-          const d4 Xt = transpose_tile(X, tr);  // A(i,j), strictly lower if i == j
+          const d4 Xt = Ns[m];  // the same block in the other layout (an L1/L2 hit)
           if (i != j) {
             save_compact(r64 + 16 * i * nr, ri, nr);
             d4 rj = load_compact(r64 + 16 * j * nr, nr);
@@ -705,7 +725,7 @@ __global__ void k_mx_factor(const float *ws, long long woff, int n, float *dst,
 using namespace bh;
 
 static const int kMxLW = 4;     // waves per instance, refinement
-static const int kMxRT = 4;     // residual tiles per wave loaded together
+static const int kMxRT = 2;     // residual tiles per wave loaded together
 static const int kMxFacLW = 1;  // waves per instance, factorization
 static const int kMxFacR = 4;   // block rows per downdate group, factorization
 static const int kMxFacQU = 2;  // steps of the downdate sum loaded together
