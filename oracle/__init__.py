@@ -38,6 +38,7 @@ def lib():
         L.orc_dpotrf_l.argtypes = [_i, _dp, _i, _dp, _i, _dp]
         L.orc_dpotrf_l.restype = _i
         L.orc_dtrsm_rltn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
+        L.orc_dtrmm_rlnn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
         L.orc_dsyrk_dpotrf_ln.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dsyrk_dpotrf_ln.restype = _i
         L.orc_dpotrs_l.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i]
@@ -110,6 +111,16 @@ def dpotrf_l(C):
     dA = np.zeros(max(m, 1))
     info = lib().orc_dpotrf_l(m, _p(C), _ld(C), _p(D), _ld(D), _p(dA))
     return D, dA[:m], info
+
+
+def dtrmm_rlnn(A, B, alpha=1.0):
+    """D = alpha * B * A with A lower triangular (only its lower part read)."""
+    A, B = _f64(A), _f64(B)
+    m, n = B.shape
+    assert A.shape == (n, n)
+    D = np.zeros((m, n), order="F")
+    lib().orc_dtrmm_rlnn(m, n, alpha, _p(A), _ld(A), _p(B), _ld(B), _p(D), _ld(D))
+    return D
 
 
 def dtrsm_rltn(L, B, alpha=1.0):

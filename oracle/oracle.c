@@ -80,6 +80,22 @@ int orc_dpotrf_l(int m, const double *C, int ldc, double *D, int ldd,
   return 0;
 }
 
+/* trmm_rlnn, §5.2.2 (trmm paragraph; options right, lower, not transposed,
+ * not unit) and §5.3 (the C step of the Riccati recursion):
+ * D = alpha * B * A with A n-by-n lower triangular and B, D m-by-n, i.e.
+ *   D[i][j] = alpha * sum_{k >= j} B[i][k] * A[k][j],  k ascending.
+ * Only the lower triangle of A (diagonal included) is read.  D must not
+ * overlap B or A. */
+void orc_dtrmm_rlnn(int m, int n, double alpha, const double *A, int lda,
+                    const double *B, int ldb, double *D, int ldd) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int k = j; k < n; ++k) s += EL(B, ldb, i, k) * EL(A, lda, k, j);
+      EL(D, ldd, i, j) = alpha * s;
+    }
+}
+
 /* trsm_rltn, §5.2.2 (trsm paragraph) and §4.7.2 (the A*L^-T step of the
  * range-space method): D = alpha * B * L^{-T} with L n-by-n lower triangular
  * (not unit) and B m-by-n, i.e. the X that solves X*L^T = alpha*B.  Row i of

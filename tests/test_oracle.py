@@ -202,6 +202,50 @@ def test_potrf_info_first_failing_pivot(bad):
     assert oracle.dpotrf_l(A)[2] == bad + 1
 
 
+# ----------------------------------------------------------------- trmm_rlnn
+
+def test_trmm_rlnn_integer_exact():
+    """Small integers: every product and partial sum is exact, so the oracle
+    must equal the exact integer product B * tril(A) computed in int64."""
+    rng = np.random.default_rng(40)
+    for m, n in ((1, 1), (5, 9), (17, 33), (40, 40)):
+        A = rng.integers(-4, 5, (n, n))
+        B = rng.integers(-4, 5, (m, n))
+        exact = B.astype(np.int64) @ np.tril(A).astype(np.int64)
+        assert np.array_equal(oracle.dtrmm_rlnn(A.astype(float), B.astype(float)), exact.astype(float))
+        assert np.array_equal(oracle.dtrmm_rlnn(A.astype(float), B.astype(float), alpha=-2.0),
+                              -2.0 * exact.astype(float))
+
+
+def test_trmm_rlnn_rational_tiny():
+    """Against exact rational arithmetic for a 3x4 times 4x4 lower product."""
+    rng = np.random.default_rng(41)
+    A = rng.uniform(-1, 1, (4, 4))
+    B = rng.uniform(-1, 1, (3, 4))
+    alpha = 0.75
+    Af, Bf = _frac_mat(A), _frac_mat(B)
+    D = oracle.dtrmm_rlnn(A, B, alpha)
+    for i in range(3):
+        for j in range(4):
+            e = Fraction(alpha) * sum(Bf[i][k] * Af[k][j] for k in range(j, 4))
+            assert abs(float(Fraction(D[i, j]) - e)) <= 4e-16 * (1 + abs(float(e)))
+
+
+def test_trmm_rlnn_reads_only_lower_and_special_cases():
+    rng = np.random.default_rng(42)
+    A = np.tril(rng.integers(-3, 4, (7, 7)).astype(float))
+    B = rng.integers(-3, 4, (5, 7)).astype(float)
+    A2 = A.copy()
+    A2[np.triu_indices(7, 1)] = np.nan
+    assert np.array_equal(oracle.dtrmm_rlnn(A2, B), oracle.dtrmm_rlnn(A, B))
+    # identity and diagonal factors scale the columns of B
+    assert np.array_equal(oracle.dtrmm_rlnn(np.eye(7), B, alpha=3.0), 3.0 * B)
+    d = np.arange(1.0, 8.0)
+    assert np.array_equal(oracle.dtrmm_rlnn(np.diag(d), B), B * d)
+    # the last column of D only sees the last column of B
+    assert np.array_equal(oracle.dtrmm_rlnn(A, B)[:, 6], B[:, 6] * A[6, 6])
+
+
 # ----------------------------------------------------------------- trsm_rltn
 
 def test_trsm_rltn_integer_recovery():
