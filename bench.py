@@ -134,6 +134,20 @@ def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
            "riccati_recursions_per_s": round(batch / ms * 1e3, 1),
            "riccati_failed": int((info != 0).sum().item())}
     del sF
+    # the C step of one stage as a separate batched trmm_rlnn: C = [B^T; A^T] L,
+    # (nu + nx) x nx times an nx x nx lower factor, m n^2 flops per instance
+    m = nu + nx
+    rng = np.random.default_rng(3)
+    sX = p.pack_batch(torch.as_tensor(rng.uniform(-1, 1, (batch, m, nx)), device=dev))
+    sLc = p.pack_batch(torch.as_tensor(np.tril(rng.uniform(-1, 1, (batch, nx, nx))), device=dev))
+    sC = p.DMatBatch(batch, m, nx)
+    _, pt = time_events(lambda: p.blasfeo_hip_dtrmm_rlnn_batched(batch, m, nx, 1.0, sLc, 0, 0, sX, 0, 0, sC, 0, 0,
+                                                                 stream), reps, 2, stream)
+    tms = float(np.median(pt))
+    out.update({"trmm_rlnn_batch_ms": round(tms, 4),
+                "trmm_rlnn_batch_gflops": round(batch * m * nx * nx / tms / 1e6, 1),
+                "trmm_rlnn_batch_config": f"{batch} x (B {m}x{nx}, A {nx}x{nx} lower)"})
+    del sX, sLc, sC
     torch.cuda.empty_cache()
     return out
 

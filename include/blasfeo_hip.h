@@ -137,6 +137,14 @@ void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
                       int bj, double beta, struct blasfeo_dmat *sC, int ci,
                       int cj, struct blasfeo_dmat *sD, int di, int dj);
 
+/* trmm_rlnn (§5.2.2, trmm paragraph; the C step of the Riccati recursion,
+ * §5.3): D <- alpha * B * A, A n-by-n lower triangular, not unit, at
+ * (ai,aj) (only its lower triangle is read); B and D m-by-n.  D must not
+ * share storage with B or A (error -10). */
+void blasfeo_dtrmm_rlnn(int m, int n, double alpha, struct blasfeo_dmat *sA,
+                        int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                        int bj, struct blasfeo_dmat *sD, int di, int dj);
+
 /* trsm_rltn (§5.2.2, §4.7.2): D <- alpha * B * A^{-T}, A n-by-n lower
  * triangular, not unit, at (ai,aj) (only its lower triangle is read; the
  * reciprocals of its diagonal are formed by the routine); B and D m-by-n.
@@ -236,6 +244,17 @@ int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,
                                  const struct blasfeo_dmat *sC, int ci,
                                  int cj, const struct blasfeo_dmat *sD,
                                  int di, int dj, void *stream);
+
+/* Uniform batch of trmm_rlnn (same sizes and offsets for every instance,
+ * instance b of each operand at its dmat's pA + b * (memsize / 8)).
+ * Returns 0, -i for bad argument i (a D sharing storage with B or A: -12),
+ * or a HIP error code. */
+int blasfeo_hip_dtrmm_rlnn_batched(int batch, int m, int n, double alpha,
+                                   const struct blasfeo_dmat *sA, int ai,
+                                   int aj, const struct blasfeo_dmat *sB,
+                                   int bi, int bj,
+                                   const struct blasfeo_dmat *sD, int di,
+                                   int dj, void *stream);
 
 int blasfeo_hip_dtrsm_rltn_batched(int batch, int m, int n, double alpha,
                                    const struct blasfeo_dmat *sA, int ai,

@@ -54,6 +54,7 @@ _SIGS = {
     "blasfeo_dgemm_nt": (None, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dsyrk_ln": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dtrsm_rltn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dtrmm_rlnn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dpotrf_l": (None, [_i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dsyrk_dpotrf_ln": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_hip_dpotrf_l_info": (None, [_i, _M, _i, _i, _M, _i, _i, _p]),
@@ -68,6 +69,7 @@ _SIGS = {
     "blasfeo_hip_dgemm_nt_batched": (_i, [_i, _i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dsyrk_ln_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dtrsm_rltn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dtrmm_rlnn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trf_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _M, _p, _p]),
@@ -284,6 +286,12 @@ def blasfeo_dtrsm_rltn(m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj):
     check_last()
 
 
+def blasfeo_dtrmm_rlnn(m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dtrmm_rlnn(m, n, alpha, sA.ref, ai, aj, sB.ref, bi, bj, sD.ref, di, dj)
+    check_last()
+
+
 def blasfeo_dpotrf_l(m, sC, ci, cj, sD, di, dj):
     _sync_stream()
     lib().blasfeo_dpotrf_l(m, sC.ref, ci, cj, sD.ref, di, dj)
@@ -323,6 +331,11 @@ def blasfeo_hip_dsyrk_ln_batched(batch, m, k, alpha, sA, ai, aj, sB, bi, bj, bet
 
 def blasfeo_hip_dtrsm_rltn_batched(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj, stream=None):
     return check(lib().blasfeo_hip_dtrsm_rltn_batched(batch, m, n, alpha, sA.ref, ai, aj, sB.ref, bi, bj,
+                                                      sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_dtrmm_rlnn_batched(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj, stream=None):
+    return check(lib().blasfeo_hip_dtrmm_rlnn_batched(batch, m, n, alpha, sA.ref, ai, aj, sB.ref, bi, bj,
                                                       sD.ref, di, dj, _stream(stream)))
 
 

@@ -1,5 +1,5 @@
-// Generic panel-major level-3 routines: gemm_nt, syrk_ln, trsm_rltn,
-// potrf_l and syrk_potrf_ln on arbitrary sub-matrices (any (ai, aj), any
+// Generic panel-major level-3 routines: gemm_nt, syrk_ln, trmm_rlnn,
+// trsm_rltn, potrf_l and syrk_potrf_ln on arbitrary sub-matrices (any (ai, aj), any
 // sizes), single instance or uniform batch (one batch index per grid row).
 //
 // These are the "generic" kernel variant of §4.4.2: every 16x16 block is
@@ -56,6 +56,45 @@ __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
 #pragma unroll
   for (int r = 0; r < 4; ++r) out[r] = beta * ct[r] + alpha * acc[r];
   store_tileT(D, 16 * ti, 16 * tj, out, SYRK);
+}
+
+// ---------------------------------------------------------------- trmm_rlnn
+// D = alpha * B * A with A lower triangular (§5.2.2, trmm paragraph; the
+// C step of the Riccati recursion, §5.3).  One wave per 16x16 block (i, j)
+// of D: D(i,j) = sum_{k >= j} B(i,k) A(k,j), i.e. a gemm_nt against A^T
+// whose k-loop starts at the block's first column (A(k,j) = 0 for k < j);
+// the A^T fragment of rows 16j..16j+15 is read column-wise from A and masked
+// to the lower triangle, so the diagonal block needs no special case.
+__device__ __forceinline__ double load_fragT_lower(const View &v, int j0, int k0) {
+  const int l = lane_id();
+  const int j = j0 + (l & 15), k = k0 + (l >> 4);  // A(k, j)
+  const bool ok = k < v.rows && j < v.cols && k >= j;
+  const double x = v.p[ok ? pm_off(v.ai + k, v.aj + j, v.cn) : pm_off(v.ai, v.aj, v.cn)];
+  return ok ? x : 0.0;
+}
+
+__global__ __launch_bounds__(64 * GW) void k_trmm_rlnn(int m, int n, double alpha,
+                                                       View A, View B, View D,
+                                                       long long sA, long long sB,
+                                                       long long sD) {
+  A = at_batch(A, sA);
+  B = at_batch(B, sB);
+  D = at_batch(D, sD);
+  const int w = wave_id();
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+  const int tile = blockIdx.x * GW + w;
+  if (tile >= tm * tn) return;
+  const int ti = tile / tn, tj = tile - ti * tn;
+  d4 acc = zero4();
+  for (int k0 = 16 * tj; k0 < n; k0 += 4) {
+    const double fa = load_fragT_lower(A, 16 * tj, k0);  // A^T rows 16tj.., cols k0..k0+3
+    const double fb = load_frag(B, 16 * ti, k0);
+    acc = mfma(fa, fb, acc);
+  }
+  d4 out;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = alpha * acc[r];
+  store_tileT(D, 16 * ti, 16 * tj, out, false);
 }
 
 // ---------------------------------------------------------------- trsm_rltn
@@ -292,6 +331,28 @@ int launch_trsm(int batch, int m, int n, double alpha, const blasfeo_dmat *sA,
   return launch_status();
 }
 
+int launch_trmm(int batch, int m, int n, double alpha, const blasfeo_dmat *sA,
+                int ai, int aj, const blasfeo_dmat *sB, int bi, int bj,
+                const blasfeo_dmat *sD, int di, int dj, hipStream_t st) {
+  if (batch == 0 || m == 0 || n == 0) return 0;
+  const int tiles = ((m + 15) / 16) * ((n + 15) / 16);
+  dim3 grid((tiles + GW - 1) / GW, batch);
+  View A = make_view(sA, ai, aj, n, n);
+  View B = make_view(sB, bi, bj, m, n);
+  View D = make_view(sD, di, dj, m, n);
+  hipLaunchKernelGGL(k_trmm_rlnn, grid, dim3(64 * GW), 0, st, m, n, alpha, A, B, D,
+                     batch_stride(sA), batch_stride(sB), batch_stride(sD));
+  return launch_status();
+}
+
+// True if the two sub-matrices share storage: same panel buffer and
+// intersecting row and column ranges.
+static bool overlaps(const blasfeo_dmat *x, int xi, int xj, int xr, int xc,
+                     const blasfeo_dmat *y, int yi, int yj, int yr, int yc) {
+  if (x->pA != y->pA || xr == 0 || xc == 0 || yr == 0 || yc == 0) return false;
+  return xi < yi + yr && yi < xi + xr && xj < yj + yc && yj < xj + xc;
+}
+
 int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
                  int aj, const blasfeo_dmat *sB, int bi, int bj,
                  const blasfeo_dmat *sC, int ci, int cj,
@@ -371,6 +432,21 @@ void blasfeo_dtrsm_rltn(int m, int n, double alpha, struct blasfeo_dmat *sA,
   if (!operand_ok(sB, bi, bj, m, n)) return set_error(-7);
   if (!operand_ok(sD, di, dj, m, n)) return set_error(-10);
   set_error(launch_trsm(1, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
+                        tl_stream()));
+}
+
+void blasfeo_dtrmm_rlnn(int m, int n, double alpha, struct blasfeo_dmat *sA,
+                        int ai, int aj, struct blasfeo_dmat *sB, int bi,
+                        int bj, struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (n < 0) return set_error(-2);
+  if (!operand_ok(sA, ai, aj, n, n)) return set_error(-4);
+  if (!operand_ok(sB, bi, bj, m, n)) return set_error(-7);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-10);
+  if (overlaps(sD, di, dj, m, n, sB, bi, bj, m, n) ||
+      overlaps(sD, di, dj, m, n, sA, ai, aj, n, n))
+    return set_error(-10);
+  set_error(launch_trmm(1, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
                         tl_stream()));
 }
 
@@ -472,6 +548,25 @@ int blasfeo_hip_dtrsm_rltn_batched(int batch, int m, int n, double alpha,
   if (!operand_ok(sB, bi, bj, m, n)) return -8;
   if (!operand_ok(sD, di, dj, m, n)) return -11;
   return launch_trsm(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
+                     (hipStream_t)stream);
+}
+
+int blasfeo_hip_dtrmm_rlnn_batched(int batch, int m, int n, double alpha,
+                                   const struct blasfeo_dmat *sA, int ai,
+                                   int aj, const struct blasfeo_dmat *sB,
+                                   int bi, int bj,
+                                   const struct blasfeo_dmat *sD, int di,
+                                   int dj, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!operand_ok(sA, ai, aj, n, n)) return -6;
+  if (!operand_ok(sB, bi, bj, m, n)) return -9;
+  if (!operand_ok(sD, di, dj, m, n)) return -12;
+  if (overlaps(sD, di, dj, m, n, sB, bi, bj, m, n) ||
+      overlaps(sD, di, dj, m, n, sA, ai, aj, n, n))
+    return -12;
+  return launch_trmm(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, sD, di, dj,
                      (hipStream_t)stream);
 }
 

@@ -147,6 +147,67 @@ def test_dsyrk_ln(m, k, off):
     assert np.all(sub[np.triu_indices(m, 1)] == SENT)
 
 
+# ------------------------------------------------------------------ trmm_rlnn
+
+@pytest.mark.parametrize("m,n", [(40, 32), (1, 1), (37, 50), (100, 17), (16, 64), (20, 130)])
+@pytest.mark.parametrize("offs", [(0, 0, 0, 0, 0, 0), (5, 3, 2, 9, 17, 1)])
+def test_dtrmm_rlnn(m, n, offs):
+    """D = alpha*B*A, A lower: element-wise parity with the oracle on ragged
+    sizes and unaligned offsets; the strictly upper part of A is poisoned and
+    every element of D outside the sub-matrix keeps its sentinel."""
+    note("trmm_rlnn", m, n, offs)
+    ai, aj, bi, bj, di, dj = offs
+    rng = np.random.default_rng(m * 13 + n)
+    A = np.tril(rng.uniform(-1, 1, (n, n)))
+    B = rng.uniform(-1, 1, (m, n))
+    sA = sentinel_mat(ai + n, aj + n)
+    sB, sD = sentinel_mat(bi + m, bj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(A + np.triu(np.full((n, n), np.nan), 1)), sA, ai, aj)
+    p.pack(dev(B), sB, bi, bj)
+    p.blasfeo_dtrmm_rlnn(m, n, -1.5, sA, ai, aj, sB, bi, bj, sD, di, dj)
+    D = host(sD)
+    assert_parity(D[di:, dj:], oracle.dtrmm_rlnn(A, B, -1.5), n, "trmm")
+    outside = np.ones_like(D, dtype=bool)
+    outside[di:, dj:] = False
+    assert np.all(D[outside] == SENT)
+
+
+def test_dtrmm_rlnn_integer_exact_and_overlap_rejected():
+    note("trmm exact")
+    rng = np.random.default_rng(7)
+    A = np.tril(rng.integers(-3, 4, (48, 48))).astype(float)
+    B = rng.integers(-3, 4, (19, 48)).astype(float)
+    sA, sB, sD = mat(A), mat(B), p.DMat(19, 48)
+    p.blasfeo_dtrmm_rlnn(19, 48, 2.0, sA, 0, 0, sB, 0, 0, sD, 0, 0)
+    assert np.array_equal(host(sD), 2.0 * (B @ A))
+    with pytest.raises(p.HipError):
+        p.blasfeo_dtrmm_rlnn(19, 48, 1.0, sA, 0, 0, sB, 0, 0, sB, 0, 0)  # D is B
+    assert np.array_equal(host(sB), B)
+
+
+def test_dtrmm_rlnn_batched_riccati_shape():
+    """The C step of the Riccati workload as a uniform batch: 4096 x
+    (B 40x32, A 32x32 lower); the output of every instance against the
+    exact-in-FP64 product of numpy on the host and 64 sampled instances
+    against the oracle."""
+    note("trmm batched 4096 x (40, 32)")
+    batch, m, n = 4096, 40, 32
+    rng = np.random.default_rng(11)
+    A = np.tril(rng.uniform(-1, 1, (batch, n, n)))
+    B = rng.uniform(-1, 1, (batch, m, n))
+    sA, sB, sD = p.pack_batch(dev(A)), p.pack_batch(dev(B)), p.DMatBatch(batch, m, n)
+    p.blasfeo_hip_dtrmm_rlnn_batched(batch, m, n, 1.0, sA, 0, 0, sB, 0, 0, sD, 0, 0)
+    torch.cuda.synchronize()
+    D = p.unpack_batch(sD).cpu().numpy()
+    ref = B @ A
+    err = np.linalg.norm(D - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    assert float(err.max()) <= 1e-13 * n
+    for b in rng.choice(batch, 64, replace=False):
+        assert_parity(D[b], oracle.dtrmm_rlnn(A[b], B[b]), n, f"trmm b={b}")
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dtrmm_rlnn_batched(batch, m, n, 1.0, sA, 0, 0, sB, 0, 0, sB, 0, 0)
+
+
 # ------------------------------------------------------------------ trsm_rltn
 
 @pytest.mark.parametrize("m,n", [(16, 64), (1, 1), (37, 50), (100, 17), (20, 130)])
