@@ -47,6 +47,7 @@ def lib():
         L.orc_berr.restype = _d
         L.orc_ric_trf.argtypes = [_i, _i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp]
         L.orc_ric_trf.restype = _i
+        L.orc_ric_trs.argtypes = [_i, _i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_spotrf_l.argtypes = [_i, _fp, _i, _fp, _i]
         L.orc_spotrf_l.restype = _i
         L.orc_spotrs_l.argtypes = [_i, _fp, _i, _fp, _fp]
@@ -179,6 +180,23 @@ def ric_trf(A, B, Q, R, PN, N):
     F = np.zeros((N * nm * nm,))
     info = lib().orc_ric_trf(nx, nu, N, _p(A), _ld(A), _p(B), _ld(B), _p(Q), _ld(Q), _p(R), _ld(R), _p(PN), _ld(PN), _p(F))
     return F.reshape(N, nm, nm).transpose(0, 2, 1).copy(), info
+
+
+def ric_trs(A, B, PN, F, b, r, q, x0):
+    """(u, x): controls (N, nu) and states (N+1, nx) of the linear-quadratic
+    problem whose stage factors F (from ric_trf) are given; b (N, nx),
+    r (N, nu), q (N+1, nx), x0 (nx,)."""
+    A, B, PN = (_f64(x) for x in (A, B, PN))
+    nx, nu = B.shape
+    N = F.shape[0]
+    Fc = np.ascontiguousarray(np.asarray(F, dtype=np.float64).transpose(0, 2, 1))  # column-major blocks
+    b, r, q, x0 = (np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (b, r, q, x0))
+    assert b.shape == (N, nx) and r.shape == (N, nu) and q.shape == (N + 1, nx) and x0.shape == (nx,)
+    u = np.zeros((N, nu))
+    x = np.zeros((N + 1, nx))
+    lib().orc_ric_trs(nx, nu, N, _p(A), _ld(A), _p(B), _ld(B), _p(PN), _ld(PN), _p(Fc), _p(b), _p(r), _p(q),
+                      _p(x0), _p(u), _p(x))
+    return u, x
 
 
 def spotrf_l(C):

@@ -247,6 +247,111 @@ int orc_ric_trf(int nx, int nu, int N, const double *A, int lda,
   return 0;
 }
 
+/* Riccati solve: the solution of the linear-quadratic control problem whose
+ * KKT matrix orc_ric_trf factors (§5.3 states the recursion as the
+ * factorization of that KKT matrix; the substitution below is the standard
+ * one of the square-root form, not printed in the paper):
+ *   minimize  sum_n 1/2 u_n'R u_n + r_n'u_n + 1/2 x_n'Q x_n + q_n'x_n
+ *             + 1/2 x_N'P_N x_N + q_N'x_N
+ *   subject to x_{n+1} = A x_n + B u_n + b_n,  x_0 given,  n = 0..N-1.
+ * With F_n = [[Lam_n, 0], [L_n, Lc_n]] the stage factors (F_n F_n' = M_n,
+ * M_n = [[R + B'P B, B'P A], [A'P B, Q + A'P A]], P = P_{n+1} = Lc_{n+1} Lc_{n+1}'
+ * and P_N given), the value function's linear term p_n follows backwards,
+ *   w = P_{n+1} b_n + p_{n+1},  m_u = r_n + B'w,  m_x = q_n + A'w,
+ *   l_n = Lam_n^{-1} m_u,       p_n = m_x - L_n l_n,       p_N = q_N,
+ * and the controls and states forwards,
+ *   u_n = -Lam_n^{-T} (L_n' x_n + l_n),  x_{n+1} = A x_n + B u_n + b_n.
+ * F is as written by orc_ric_trf (N column-major (nu+nx)^2 blocks); only
+ * the lower triangle of PN is read.  b: N x nx, r: N x nu, q: (N+1) x nx,
+ * u: N x nu, x: (N+1) x nx, all row n contiguous. */
+void orc_ric_trs(int nx, int nu, int N, const double *A, int lda,
+                 const double *B, int ldb, const double *PN, int ldp,
+                 const double *F, const double *b, const double *r,
+                 const double *q, const double *x0, double *u, double *x) {
+  int nm = nu + nx;
+  double *p = (double *)calloc((size_t)nx, sizeof(double));
+  double *w = (double *)calloc((size_t)nx, sizeof(double));
+  double *s = (double *)calloc((size_t)nx, sizeof(double));
+  double *m = (double *)calloc((size_t)nm, sizeof(double));
+  double *l = (double *)calloc((size_t)N * nu + 1, sizeof(double));
+  for (int i = 0; i < nx; ++i) p[i] = q[(size_t)N * nx + i];
+  for (int n = N - 1; n >= 0; --n) {
+    const double *bn = b + (size_t)n * nx;
+    /* w = P_{n+1} b_n + p_{n+1} */
+    if (n == N - 1) {
+      for (int i = 0; i < nx; ++i) {
+        double t = 0.0;
+        for (int k = 0; k < nx; ++k)
+          t += (k <= i ? EL(PN, ldp, i, k) : EL(PN, ldp, k, i)) * bn[k];
+        w[i] = t + p[i];
+      }
+    } else {
+      const double *Fn1 = F + (size_t)(n + 1) * nm * nm;  /* Lc_{n+1} = its trailing block */
+      for (int j = 0; j < nx; ++j) {                      /* s = Lc' b */
+        double t = 0.0;
+        for (int i = j; i < nx; ++i) t += EL(Fn1, nm, nu + i, nu + j) * bn[i];
+        s[j] = t;
+      }
+      for (int i = 0; i < nx; ++i) {                      /* w = Lc s + p */
+        double t = 0.0;
+        for (int k = 0; k <= i; ++k) t += EL(Fn1, nm, nu + i, nu + k) * s[k];
+        w[i] = t + p[i];
+      }
+    }
+    /* m = [r_n + B'w; q_n + A'w] */
+    for (int j = 0; j < nu; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < nx; ++i) t += EL(B, ldb, i, j) * w[i];
+      m[j] = r[(size_t)n * nu + j] + t;
+    }
+    for (int j = 0; j < nx; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < nx; ++i) t += EL(A, lda, i, j) * w[i];
+      m[nu + j] = q[(size_t)n * nx + j] + t;
+    }
+    /* l_n = Lam_n^{-1} m_u (forward substitution), p_n = m_x - L_n l_n */
+    const double *Fn = F + (size_t)n * nm * nm;
+    double *ln = l + (size_t)n * nu;
+    for (int i = 0; i < nu; ++i) {
+      double t = m[i];
+      for (int k = 0; k < i; ++k) t -= EL(Fn, nm, i, k) * ln[k];
+      ln[i] = t / EL(Fn, nm, i, i);
+    }
+    for (int i = 0; i < nx; ++i) {
+      double t = 0.0;
+      for (int k = 0; k < nu; ++k) t += EL(Fn, nm, nu + i, k) * ln[k];
+      p[i] = m[nu + i] - t;
+    }
+  }
+  for (int i = 0; i < nx; ++i) x[i] = x0[i];
+  for (int n = 0; n < N; ++n) {
+    const double *Fn = F + (size_t)n * nm * nm;
+    const double *xn = x + (size_t)n * nx;
+    double *un = u + (size_t)n * nu;
+    /* v = L_n' x_n + l_n, then u_n = -Lam_n^{-T} v (back substitution) */
+    for (int j = 0; j < nu; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < nx; ++i) t += EL(Fn, nm, nu + i, j) * xn[i];
+      m[j] = t + l[(size_t)n * nu + j];
+    }
+    for (int i = nu - 1; i >= 0; --i) {
+      double t = m[i];
+      for (int k = i + 1; k < nu; ++k) t -= EL(Fn, nm, k, i) * un[k];
+      un[i] = t / EL(Fn, nm, i, i);
+    }
+    for (int i = 0; i < nu; ++i) un[i] = -un[i];
+    /* x_{n+1} = A x_n + B u_n + b_n */
+    double *xn1 = x + (size_t)(n + 1) * nx;
+    for (int i = 0; i < nx; ++i) {
+      double t = 0.0;
+      for (int k = 0; k < nx; ++k) t += EL(A, lda, i, k) * xn[k];
+      for (int k = 0; k < nu; ++k) t += EL(B, ldb, i, k) * un[k];
+      xn1[i] = t + b[(size_t)n * nx + i];
+    }
+  }
+  free(p); free(w); free(s); free(m); free(l);
+}
+
 /* ---- single-precision pieces of the mixed-precision solve ----------------
  * Not from the paper: the FP32 factor-and-solve that iterative refinement
  * starts from.  Same definitions as orc_dpotrf_l / orc_dpotrs_l, with every

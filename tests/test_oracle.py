@@ -365,6 +365,83 @@ def test_riccati_closed_form_no_input():
         assert np.allclose(np.diag(Lc), np.sqrt(N - n + 1.0), rtol=4 * N * U, atol=0)
 
 
+def _dense_kkt_lq(A, B, Q, R, PN, b, r, q, x0):
+    """Solution (u, x) of the linear-quadratic problem from its full KKT
+    system, assembled and solved densely (numpy LU): variables
+    z = [u_0, x_1, u_1, x_2, ..., u_{N-1}, x_N], one multiplier per dynamics
+    equation x_{n+1} - A x_n - B u_n = b_n."""
+    nx, nu = B.shape
+    N = b.shape[0]
+    nz = N * (nu + nx)
+    H = np.zeros((nz, nz))
+    g = np.zeros(nz)
+    G = np.zeros((N * nx, nz))
+    h = np.zeros(N * nx)
+    iu = lambda n: n * (nu + nx)            # noqa: E731
+    ix = lambda n: (n - 1) * (nu + nx) + nu  # noqa: E731  (x_n for n >= 1)
+    for n in range(N):
+        H[iu(n):iu(n) + nu, iu(n):iu(n) + nu] = R
+        g[iu(n):iu(n) + nu] = r[n]
+        if n >= 1:
+            H[ix(n):ix(n) + nx, ix(n):ix(n) + nx] = Q
+            g[ix(n):ix(n) + nx] = q[n]
+    H[ix(N):ix(N) + nx, ix(N):ix(N) + nx] = PN
+    g[ix(N):ix(N) + nx] = q[N]
+    for n in range(N):
+        rows = slice(n * nx, (n + 1) * nx)
+        G[rows, ix(n + 1):ix(n + 1) + nx] = np.eye(nx)
+        G[rows, iu(n):iu(n) + nu] = -B
+        if n >= 1:
+            G[rows, ix(n):ix(n) + nx] = -A
+            h[rows] = b[n]
+        else:
+            h[rows] = b[0] + A @ x0
+    K = np.block([[H, G.T], [G, np.zeros((N * nx, N * nx))]])
+    sol = np.linalg.solve(K, np.concatenate([-g, h]))
+    z = sol[:nz]
+    u = np.array([z[iu(n):iu(n) + nu] for n in range(N)])
+    x = np.array([x0] + [z[ix(n):ix(n) + nx] for n in range(1, N + 1)])
+    return u, x
+
+
+@pytest.mark.parametrize("nx,nu,N", [(1, 1, 1), (3, 2, 4), (5, 3, 7), (32, 8, 20)])
+def test_riccati_solve_matches_dense_kkt(nx, nu, N):
+    """The backward/forward substitution on the stage factors gives the same
+    controls and states as the dense KKT solve of the whole problem."""
+    rng = np.random.default_rng(nx * 10 + N)
+    A = np.eye(nx) + 0.1 * rng.standard_normal((nx, nx))
+    B = rng.standard_normal((nx, nu)) / 2
+    G = rng.standard_normal((nx, nx))
+    Q = G @ G.T / nx + np.eye(nx)
+    R = 0.5 * np.eye(nu) + 0.1 * np.ones((nu, nu))
+    PN = 2.0 * np.eye(nx)
+    b, r, q = rng.standard_normal((N, nx)), rng.standard_normal((N, nu)), rng.standard_normal((N + 1, nx))
+    x0 = rng.standard_normal(nx)
+    F, info = oracle.ric_trf(A, B, Q, R, PN, N)
+    assert info == 0
+    u, x = oracle.ric_trs(A, B, PN, F, b, r, q, x0)
+    ud, xd = _dense_kkt_lq(A, B, Q, R, PN, b, r, q, x0)
+    assert np.linalg.norm(u - ud) <= 1e-10 * np.linalg.norm(ud)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    # the dynamics hold exactly as computed (same order of operations)
+    for n in range(N):
+        assert np.allclose(x[n + 1], A @ x[n] + B @ u[n] + b[n], rtol=0, atol=1e-12 * (1 + np.abs(x[n + 1]).max()))
+
+
+def test_riccati_solve_scalar_closed_form():
+    """One state, one input, one stage, by hand: minimizing
+    1/2 R u^2 + r u + 1/2 P (a x0 + c u + d)^2 + q1 (a x0 + c u + d)
+    over u gives u = -(r + c (P (a x0 + d) + q1)) / (R + c^2 P)."""
+    a, c, d, R, r, P, q1, x0 = 0.9, 0.5, 0.2, 0.3, -0.4, 2.0, 0.7, 1.5
+    F, info = oracle.ric_trf(np.array([[a]]), np.array([[c]]), np.array([[1.0]]), np.array([[R]]),
+                             np.array([[P]]), 1)
+    u, x = oracle.ric_trs(np.array([[a]]), np.array([[c]]), np.array([[P]]), F, np.array([[d]]),
+                          np.array([[r]]), np.array([[0.3], [q1]]), np.array([x0]))
+    ue = -(r + c * (P * (a * x0 + d) + q1)) / (R + c * c * P)
+    assert abs(u[0, 0] - ue) <= 1e-15 * 4
+    assert abs(x[1, 0] - (a * x0 + c * ue + d)) <= 1e-15 * 8
+
+
 def test_riccati_matches_classical_form():
     """Square-root recursion vs the classical Riccati difference equation with
     explicit P (numpy, independent algorithm)."""
