@@ -133,6 +133,17 @@ def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
     out = {"riccati_ms": round(ms, 3), "riccati_gflops": round(fl / ms / 1e6, 1),
            "riccati_recursions_per_s": round(batch / ms * 1e3, 1),
            "riccati_failed": int((info != 0).sum().item())}
+    # the solve of the linear-quadratic problem on those factors
+    rng = np.random.default_rng(5)
+    vb, vr = (torch.as_tensor(rng.standard_normal((batch, N, k)), device=dev) for k in (nx, nu))
+    vq, vx0 = torch.as_tensor(rng.standard_normal((batch, N + 1, nx)), device=dev), \
+        torch.as_tensor(rng.standard_normal((batch, nx)), device=dev)
+    vu = torch.empty((batch, N, nu), dtype=torch.float64, device=dev)
+    vx = torch.empty((batch, N + 1, nx), dtype=torch.float64, device=dev)
+    _, ps = time_events(lambda: p.blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA, sB, sP, sF, vb, vr, vq, vx0,
+                                                               vu, vx, stream), reps, 2, stream)
+    out.update({"riccati_solve_ms": round(float(np.median(ps)), 3),
+                "riccati_solves_per_s": round(batch / float(np.median(ps)) * 1e3, 1)})
     del sF
     # the C step of one stage as a separate batched trmm_rlnn: C = [B^T; A^T] L,
     # (nu + nx) x nx times an nx x nx lower factor, m n^2 flops per instance

@@ -304,6 +304,32 @@ int blasfeo_hip_dric_trf_batched(int batch, int nx, int nu, int N,
                                  const struct blasfeo_dmat *sF, int *info,
                                  void *stream);
 
+/* Solution of the linear-quadratic problem whose KKT matrix the recursion
+ * above factors (§5.3 gives the factorization; the substitution is the
+ * standard one of the square-root form):
+ *   min sum_n 1/2 u_n'R u_n + r_n'u_n + 1/2 x_n'Q x_n + q_n'x_n
+ *       + 1/2 x_N'P_N x_N + q_N'x_N,
+ *   s.t. x_{n+1} = A x_n + B u_n + b_n (n = 0..N-1), x_0 given.
+ * Backward: w = P_{n+1} b_n + p_{n+1}, l_n = Lambda_n^{-1}(r_n + B'w),
+ * p_n = q_n + A'w - L_n l_n, p_N = q_N, with P_{n+1} = Lc_{n+1} Lc_{n+1}'
+ * (P_N for n = N-1); forward: u_n = -Lambda_n^{-T}(L_n' x_n + l_n),
+ * x_{n+1} = A x_n + B u_n + b_n.  sA, sB, sP and sF as given to and written
+ * by blasfeo_hip_dric_trf_batched (same batch, nx, nu, N; Q and R enter
+ * through F).  Vectors are plain device arrays, problem-major, stage rows
+ * contiguous: b[(p*N + n)*nx + i], r[(p*N + n)*nu + i],
+ * q[(p*(N+1) + n)*nx + i], x0[p*nx + i]; outputs u[(p*N + n)*nu + i] and
+ * x[(p*(N+1) + n)*nx + i] (x_0 copied).  The caller owns every buffer.
+ * Returns 0, -i for bad argument i, or a HIP error code.  The factors must
+ * come from a factorization with info = 0 (no check is made). */
+int blasfeo_hip_dric_trs_batched(int batch, int nx, int nu, int N,
+                                 const struct blasfeo_dmat *sA,
+                                 const struct blasfeo_dmat *sB,
+                                 const struct blasfeo_dmat *sP,
+                                 const struct blasfeo_dmat *sF,
+                                 const double *b, const double *r,
+                                 const double *q, const double *x0,
+                                 double *u, double *x, void *stream);
+
 /* ------------------------------------------------------------------------
  * Uneven batches: plans.  A plan is created once for a list of orders and
  * executed many times (the embedded-optimization pattern of §2: the same

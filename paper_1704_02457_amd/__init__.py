@@ -73,6 +73,7 @@ _SIGS = {
     "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trf_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _M, _p, _p]),
+    "blasfeo_hip_dric_trs_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_pack_dmat_indexed": (_i, [_i, _i, _i, _p, _i, _ll, _p, _p, _i, _p]),
     "blasfeo_hip_dposv_vbatched_plan": (_i, [_i, _p, _i, ctypes.POINTER(_p)]),
     "blasfeo_hip_plan_layout": (_i, [_p, _p, _p, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
@@ -342,6 +343,11 @@ def blasfeo_hip_dtrmm_rlnn_batched(batch, m, n, alpha, sA, ai, aj, sB, bi, bj, s
 def blasfeo_hip_dpotrf_l_batched(batch, m, sC, ci, cj, sD, di, dj, info, stream=None):
     return check(lib().blasfeo_hip_dpotrf_l_batched(batch, m, sC.ref, ci, cj, sD.ref, di, dj, _ptr(info),
                                                     _stream(stream)))
+
+
+def blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA, sB, sP, sF, b, r, q, x0, u, x, stream=None):
+    return check(lib().blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA.ref, sB.ref, sP.ref, sF.ref, _ptr(b), _ptr(r),
+                                                    _ptr(q), _ptr(x0), _ptr(u), _ptr(x), _stream(stream)))
 
 
 def blasfeo_hip_dric_trf_batched(batch, nx, nu, N, sA, sB, sQ, sR, sP, sF, info, stream=None):

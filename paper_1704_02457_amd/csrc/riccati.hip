@@ -201,6 +201,158 @@ static void launch_ric(const RicArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((k_ric_trf<NUB, NXB>), dim3(a.batch), dim3(64), 0, st, a);
 }
 
+// ---------------------------------------------------------------- solve
+// The solution of the linear-quadratic problem whose KKT matrix the
+// recursion above factors (the standard substitution of the square-root
+// form): a backward pass for the linear term p_n of the value function,
+//   w = P_{n+1} b_n + p_{n+1},  m = [r_n + B'w; q_n + A'w],
+//   l_n = Lambda_n^{-1} m_u,    p_n = m_x - L_n l_n,   p_N = q_N,
+// with P_{n+1} = Lc_{n+1} Lc_{n+1}' taken from the next stage's factor
+// (P_N itself for the last stage), then a forward pass
+//   u_n = -Lambda_n^{-T} (L_n' x_n + l_n),   x_{n+1} = A x_n + B u_n + b_n.
+// All of it is matrix-vector work on order <= 48: one wave per problem,
+// lane i owning row i of every vector, vectors broadcast through LDS and
+// the two nu-by-nu triangular solves column by column.
+struct RicSolveArgs {
+  int batch, nx, nu, N;
+  View A, B, P;
+  long long sA, sB, sP;
+  const double *F;  // stage factors as written by k_ric_trf
+  int cnF;
+  long long sF;
+  const double *b, *r, *q, *x0;
+  double *u, *x;
+};
+
+__device__ __forceinline__ double vel(const View &v, int i, int j) {
+  return v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
+}
+
+__global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
+  __shared__ double sv[4][64];
+  const long long pb = blockIdx.x;
+  if (pb >= a.batch) return;
+  const int l = lane_id();
+  const int nx = a.nx, nu = a.nu, N = a.N, nm = nu + nx;
+  View A = a.A, B = a.B, P = a.P;
+  A.p += pb * a.sA;
+  B.p += pb * a.sB;
+  P.p += pb * a.sP;
+  auto Fv = [&](int n) {
+    return View{const_cast<double *>(a.F) + (pb * N + n) * a.sF, a.cnF, 0, 0, nm, nm};
+  };
+  const double *bv = a.b + pb * N * nx, *rv = a.r + pb * N * nu;
+  const double *qv = a.q + pb * (N + 1) * nx, *x0 = a.x0 + pb * nx;
+  double *u = a.u + pb * N * nu, *x = a.x + pb * (N + 1) * nx;
+  double *vt = sv[0], *vm = sv[1], *vp = sv[2], *vx = sv[3];
+
+  // ------------------------------------------------ backward: p_n and l_n
+  if (l < nx) vp[l] = qv[(long long)N * nx + l];
+  for (int n = N - 1; n >= 0; --n) {
+    if (l < nx) vt[l] = bv[(long long)n * nx + l];
+    wave_sync();
+    double w = 0.0;
+    if (n == N - 1) {
+      // P_N b (lower triangle of P_N read)
+      if (l < nx)
+        #pragma unroll 8
+        for (int k = 0; k < nx; ++k) w += vel(P, max(l, k), min(l, k)) * vt[k];
+    } else {
+      const View Fn1 = Fv(n + 1);
+      double sj = 0.0;  // s = Lc' b, Lc = trailing block of F_{n+1}
+      if (l < nx)
+        #pragma unroll 8
+        for (int i = l; i < nx; ++i) sj += vel(Fn1, nu + i, nu + l) * vt[i];
+      wave_sync();
+      if (l < nx) vt[l] = sj;
+      wave_sync();
+      if (l < nx)
+        #pragma unroll 8
+        for (int k = 0; k <= l; ++k) w += vel(Fn1, nu + l, nu + k) * vt[k];
+    }
+    if (l < nx) w += vp[l];
+    wave_sync();
+    if (l < nx) vt[l] = w;
+    wave_sync();
+    // m = [r_n + B'w; q_n + A'w], lane = row of m
+    double mv = 0.0;
+    if (l < nu) {
+      mv = rv[(long long)n * nu + l];
+      #pragma unroll 8
+      for (int i = 0; i < nx; ++i) mv += vel(B, i, l) * vt[i];
+    } else if (l < nm) {
+      mv = qv[(long long)n * nx + l - nu];
+      #pragma unroll 8
+      for (int i = 0; i < nx; ++i) mv += vel(A, i, l - nu) * vt[i];
+    }
+    if (l < nm) vm[l] = mv;
+    wave_sync();
+    // l_n = Lambda_n^{-1} m_u, column by column
+    const View Fn = Fv(n);
+    for (int k = 0; k < nu; ++k) {
+      const double lk = vm[k] / vel(Fn, k, k);
+      wave_sync();
+      if (l == k) vm[l] = lk;
+      if (l > k && l < nu) vm[l] -= vel(Fn, l, k) * lk;
+      wave_sync();
+    }
+    if (l < nu) u[(long long)n * nu + l] = vm[l];  // l_n, overwritten by u_n below
+    double pn = 0.0;
+    if (l >= nu && l < nm) {
+      pn = vm[l];
+      #pragma unroll 8
+      for (int k = 0; k < nu; ++k) pn -= vel(Fn, l, k) * vm[k];
+    }
+    wave_sync();
+    if (l >= nu && l < nm) vp[l - nu] = pn;
+    wave_sync();
+  }
+
+  // ------------------------------------------------ forward: u_n and x_n
+  if (l < nx) {
+    vx[l] = x0[l];
+    x[l] = x0[l];
+  }
+  for (int n = 0; n < N; ++n) {
+    const View Fn = Fv(n);
+    wave_sync();
+    double v = 0.0;  // L_n' x_n + l_n
+    if (l < nu) {
+      #pragma unroll 8
+      for (int i = 0; i < nx; ++i) v += vel(Fn, nu + i, l) * vx[i];
+      v += u[(long long)n * nu + l];
+      vm[l] = v;
+    }
+    wave_sync();
+    for (int k = nu - 1; k >= 0; --k) {  // Lambda_n^T y = v, row by row from the bottom
+      const double yk = vm[k] / vel(Fn, k, k);
+      wave_sync();
+      if (l == k) vm[l] = yk;
+      if (l < k) vm[l] -= vel(Fn, k, l) * yk;
+      wave_sync();
+    }
+    if (l < nu) {
+      const double un = -vm[l];
+      u[(long long)n * nu + l] = un;
+      vm[l] = un;
+    }
+    wave_sync();
+    double xn = 0.0;
+    if (l < nx) {
+      #pragma unroll 8
+      for (int k = 0; k < nx; ++k) xn += vel(A, l, k) * vx[k];
+      #pragma unroll 8
+      for (int k = 0; k < nu; ++k) xn += vel(B, l, k) * vm[k];
+      xn += bv[(long long)n * nx + l];
+    }
+    wave_sync();
+    if (l < nx) {
+      vx[l] = xn;
+      x[(long long)(n + 1) * nx + l] = xn;
+    }
+  }
+}
+
 }  // namespace bh
 
 using namespace bh;
@@ -245,5 +397,49 @@ extern "C" int blasfeo_hip_dric_trf_batched(
     launch_ric<1, 1>(a, st);
   else
     launch_ric<1, 2>(a, st);
+  return launch_status();
+}
+
+extern "C" int blasfeo_hip_dric_trs_batched(
+    int batch, int nx, int nu, int N, const struct blasfeo_dmat *sA,
+    const struct blasfeo_dmat *sB, const struct blasfeo_dmat *sP,
+    const struct blasfeo_dmat *sF, const double *b, const double *r,
+    const double *q, const double *x0, double *u, double *x, void *stream) {
+  if (batch < 0) return -1;
+  if (nx < 1 || nx > 32) return -2;
+  if (nu < 1 || nu > 16) return -3;
+  if (N < 1) return -4;
+  if (!operand_ok(sA, 0, 0, nx, nx)) return -5;
+  if (!operand_ok(sB, 0, 0, nx, nu)) return -6;
+  if (!operand_ok(sP, 0, 0, nx, nx)) return -7;
+  if (!operand_ok(sF, 0, 0, nu + nx, nu + nx)) return -8;
+  if (batch == 0) return 0;
+  if (!b) return -9;
+  if (!r) return -10;
+  if (!q) return -11;
+  if (!x0) return -12;
+  if (!u) return -13;
+  if (!x) return -14;
+  RicSolveArgs a;
+  a.batch = batch;
+  a.nx = nx;
+  a.nu = nu;
+  a.N = N;
+  a.A = make_view(sA, 0, 0, nx, nx);
+  a.B = make_view(sB, 0, 0, nx, nu);
+  a.P = make_view(sP, 0, 0, nx, nx);
+  a.sA = batch_stride(sA);
+  a.sB = batch_stride(sB);
+  a.sP = batch_stride(sP);
+  a.F = sF->pA;
+  a.cnF = sF->cn;
+  a.sF = batch_stride(sF);
+  a.b = b;
+  a.r = r;
+  a.q = q;
+  a.x0 = x0;
+  a.u = u;
+  a.x = x;
+  hipLaunchKernelGGL(k_ric_trs, dim3(batch), dim3(64), 0, (hipStream_t)stream, a);
   return launch_status();
 }

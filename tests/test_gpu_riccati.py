@@ -125,3 +125,92 @@ def test_riccati_bitwise_deterministic():
     F2, i2 = run(d, 5)
     assert np.array_equal(np.nan_to_num(F1, nan=7.0), np.nan_to_num(F2, nan=7.0))
     assert np.array_equal(i1, i2)
+
+
+# ------------------------------------------------------------------ solve
+
+def lq_data(batch, nx, nu, N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((batch, N, nx)), rng.standard_normal((batch, N, nu)),
+            rng.standard_normal((batch, N + 1, nx)), rng.standard_normal((batch, nx)))
+
+
+def solve_gpu(d, N, vecs):
+    batch, nx, nu = d["B"].shape
+    nm = nx + nu
+    sA, sB = p.pack_batch(dev(d["A"])), p.pack_batch(dev(d["B"]))
+    low = lambda X: np.where(np.tril(np.ones(X.shape[1:], bool))[None], X, np.nan)  # noqa: E731
+    sQ, sR, sP = p.pack_batch(dev(low(d["Q"]))), p.pack_batch(dev(low(d["R"]))), p.pack_batch(dev(low(d["PN"])))
+    sF = p.DMatBatch(batch * N, nm, nm, fill=np.nan)
+    info = torch.full((batch,), -9, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dric_trf_batched(batch, nx, nu, N, sA, sB, sQ, sR, sP, sF, info)
+    b, r, q, x0 = (dev(v) for v in vecs)
+    u = torch.full((batch, N, nu), np.nan, dtype=torch.float64, device=DEV)
+    x = torch.full((batch, N + 1, nx), np.nan, dtype=torch.float64, device=DEV)
+    p.blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA, sB, sP, sF, b, r, q, x0, u, x)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), x.cpu().numpy(), info.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("nx,nu,N", [(32, 8, 20), (32, 8, 1), (20, 3, 5), (16, 16, 4), (5, 2, 7), (32, 16, 3), (1, 1, 6)])
+def test_riccati_solve_parity(nx, nu, N):
+    """Controls and states of the linear-quadratic problem from the GPU
+    factorization and solve against the oracle's factorization and solve
+    (itself pinned against a dense KKT solve); bound 1e-13 * N * (nx + nu)
+    relative, the per-stage bound of the factors accumulated over the
+    stages."""
+    note("riccati solve", nx, nu, N)
+    batch = 9
+    d = synth.riccati_batch(batch, seed=5, nx=nx, nu=nu)
+    rng = np.random.default_rng(nx * 3 + nu)
+    for b in range(0, batch, 2):
+        G = rng.standard_normal((nu, nu))
+        d["R"][b] = G @ G.T / nu + 0.1 * np.eye(nu)
+    vecs = lq_data(batch, nx, nu, N, seed=nx + N)
+    u, x, info = solve_gpu(d, N, vecs)
+    assert np.all(info == 0)
+    tol = 1e-13 * N * (nx + nu)
+    for b in range(batch):
+        F, inf = oracle.ric_trf(d["A"][b], d["B"][b], d["Q"][b], d["R"][b], d["PN"][b], N)
+        assert inf == 0
+        ur, xr = oracle.ric_trs(d["A"][b], d["B"][b], d["PN"][b], F, vecs[0][b], vecs[1][b], vecs[2][b], vecs[3][b])
+        assert rel(u[b], ur) <= tol, (b, rel(u[b], ur))
+        assert rel(x[b], xr) <= tol, (b, rel(x[b], xr))
+        assert np.array_equal(x[b, 0], vecs[3][b])
+
+
+def test_riccati_solve_full_size():
+    """The Riccati workload (4096 problems, nx = 32, nu = 8, N = 20): every
+    problem's trajectory satisfies the dynamics, and 16 sampled problems
+    match the oracle."""
+    note("riccati solve full size")
+    batch, nx, nu, N = 4096, 32, 8, 20
+    d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
+    vecs = lq_data(batch, nx, nu, N, seed=6)
+    u, x, info = solve_gpu(d, N, vecs)
+    assert np.all(info == 0)
+    pred = np.einsum("bij,bnj->bni", d["A"], x[:, :-1]) + np.einsum("bij,bnj->bni", d["B"], u) + vecs[0]
+    assert float(np.abs(pred - x[:, 1:]).max()) <= 1e-11 * (1 + float(np.abs(x).max()))
+    for b in np.random.default_rng(7).choice(batch, 16, replace=False):
+        F, _ = oracle.ric_trf(d["A"][b], d["B"][b], d["Q"][b], d["R"][b], d["PN"][b], N)
+        ur, xr = oracle.ric_trs(d["A"][b], d["B"][b], d["PN"][b], F, vecs[0][b], vecs[1][b], vecs[2][b], vecs[3][b])
+        assert rel(u[b], ur) <= 1e-13 * N * (nx + nu)
+        assert rel(x[b], xr) <= 1e-13 * N * (nx + nu)
+
+
+def test_riccati_solve_argument_errors():
+    note("riccati solve errors")
+    d = synth.riccati_batch(2, seed=3, nx=4, nu=2)
+    sA, sB, sP = p.pack_batch(dev(d["A"])), p.pack_batch(dev(d["B"])), p.pack_batch(dev(d["PN"]))
+    sF = p.DMatBatch(2 * 3, 6, 6, fill=0.0)
+    v = torch.zeros(64, dtype=torch.float64, device=DEV)
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dric_trs_batched(2, 33, 2, 3, sA, sB, sP, sF, v, v, v, v, v, v)
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dric_trs_batched(2, 4, 2, 0, sA, sB, sP, sF, v, v, v, v, v, v)
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dric_trs_batched(2, 4, 2, 3, sA, sB, sP, sF, v, v, None, v, v, v)
