@@ -39,6 +39,8 @@ def lib():
         L.orc_dpotrf_l.restype = _i
         L.orc_dtrsm_rltn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
         L.orc_dtrmm_rlnn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
+        L.orc_dpotrf_l_mn.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp]
+        L.orc_dpotrf_l_mn.restype = _i
         L.orc_dsyrk_dpotrf_ln.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dsyrk_dpotrf_ln.restype = _i
         L.orc_dpotrs_l.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i]
@@ -112,6 +114,17 @@ def dpotrf_l(C):
     dA = np.zeros(max(m, 1))
     info = lib().orc_dpotrf_l(m, _p(C), _ld(C), _p(D), _ld(D), _p(dA))
     return D, dA[:m], info
+
+
+def dpotrf_l_mn(C, n):
+    """(D, dA, info): D = [L; A L^{-T}] for the stacked m-by-n C = [H; A]."""
+    C = _f64(C)
+    m = C.shape[0]
+    assert C.shape[1] == n and m >= n
+    D = np.zeros((m, n), order="F")
+    dA = np.zeros(max(n, 1))
+    info = lib().orc_dpotrf_l_mn(m, n, _p(C), _ld(C), _p(D), _ld(D), _p(dA))
+    return D, dA[:n], info
 
 
 def dtrmm_rlnn(A, B, alpha=1.0):

@@ -80,6 +80,33 @@ int orc_dpotrf_l(int m, const double *C, int ldc, double *D, int ldd,
   return 0;
 }
 
+/* potrf_l_mn, §4.7.2 (stacking matrices): the non-square Cholesky
+ * factorization of the stacked m-by-n matrix C = [H; A] (m >= n, H n-by-n
+ * SPD): D = [L; A L^{-T}] with L L^T = H, i.e. potrf_l on the top block and
+ * trsm_rltn on the rows below in one left-looking sweep over the n columns
+ * (the rows run to m instead of n).  Only the lower triangle of the top
+ * block and all of the bottom block are read.  dA[j] = 1/L[j][j] (n
+ * entries).  Returns 0 or the 1-based index of the first pivot that is not
+ * positive. */
+int orc_dpotrf_l_mn(int m, int n, const double *C, int ldc, double *D,
+                    int ldd, double *dA) {
+  for (int j = 0; j < n; ++j) {
+    double d = EL(C, ldc, j, j);
+    for (int k = 0; k < j; ++k) d -= EL(D, ldd, j, k) * EL(D, ldd, j, k);
+    if (!(d > 0.0)) return j + 1;
+    double ljj = sqrt(d);
+    double inv = 1.0 / ljj;
+    EL(D, ldd, j, j) = ljj;
+    if (dA) dA[j] = inv;
+    for (int i = j + 1; i < m; ++i) {
+      double s = EL(C, ldc, i, j);
+      for (int k = 0; k < j; ++k) s -= EL(D, ldd, i, k) * EL(D, ldd, j, k);
+      EL(D, ldd, i, j) = s * inv;
+    }
+  }
+  return 0;
+}
+
 /* trmm_rlnn, §5.2.2 (trmm paragraph; options right, lower, not transposed,
  * not unit) and §5.3 (the C step of the Riccati recursion):
  * D = alpha * B * A with A n-by-n lower triangular and B, D m-by-n, i.e.

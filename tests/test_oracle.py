@@ -202,6 +202,62 @@ def test_potrf_info_first_failing_pivot(bad):
     assert oracle.dpotrf_l(A)[2] == bad + 1
 
 
+# ----------------------------------------------------------------- potrf_l_mn (stacking)
+
+def test_potrf_l_mn_exact_stacked():
+    """C = [L L^T; Y L^T] from a small-integer L with power-of-two diagonal
+    and an integer Y is exact in FP64, and so is every step of the
+    factorization: the result must be [L; Y] exactly."""
+    for m, n, seed in ((5, 3, 50), (40, 24, 51), (70, 33, 52), (16, 16, 53)):
+        L, LL = synth.small_integer_factor(n, seed=seed)
+        Y = np.random.default_rng(seed).integers(-3, 4, (m - n, n)).astype(float)
+        C = np.vstack([LL, Y @ L.T])
+        C[:n][np.triu_indices(n, 1)] = np.nan  # the top block's upper part is not read
+        D, dA, info = oracle.dpotrf_l_mn(C, n)
+        assert info == 0
+        assert np.array_equal(D, np.vstack([L, Y]))
+        assert np.array_equal(dA, 1.0 / np.diag(L))
+
+
+def test_potrf_l_mn_square_is_potrf_and_failure():
+    rng = np.random.default_rng(54)
+    G = rng.standard_normal((9, 9))
+    H = G @ G.T + 9 * np.eye(9)
+    D, dA, info = oracle.dpotrf_l_mn(H, 9)
+    Lr, dAr, ir = oracle.dpotrf_l(H)
+    assert info == ir == 0 and np.array_equal(D, Lr) and np.array_equal(dA, dAr)
+    C = np.vstack([H, rng.standard_normal((4, 9))])
+    C[5, 5] = -50.0
+    assert oracle.dpotrf_l_mn(C, 9)[2] == 6
+
+
+def test_range_space_chain_matches_dense_kkt():
+    """The range-space method of the stacking passage: potrf_l_mn([H; A]) =
+    [L; Y], then chol(Y Y^T) = chol(A H^-1 A^T); solving the normal
+    equations with it gives the multipliers and the primal solution of the
+    dense KKT system."""
+    rng = np.random.default_rng(55)
+    n, ma = 24, 10
+    G = rng.standard_normal((n, n))
+    H = G @ G.T / n + np.eye(n)
+    A = rng.standard_normal((ma, n))
+    g, bvec = rng.standard_normal(n), rng.standard_normal(ma)
+    D, _, info = oracle.dpotrf_l_mn(np.vstack([H, A]), n)
+    assert info == 0
+    L, Y = D[:n], D[n:]
+    Ls, _, info2 = oracle.dsyrk_dpotrf_ln(Y, Y, np.zeros((ma, ma)))
+    assert info2 == 0
+    # normal equations A H^-1 A^T lam = b - A H^-1 g, with H^-1 = L^-T L^-1
+    Hinv_g = np.linalg.solve(L.T, np.linalg.solve(L, g))
+    rhs = bvec - A @ Hinv_g
+    lam = np.linalg.solve(Ls.T, np.linalg.solve(Ls, rhs))
+    x = -np.linalg.solve(L.T, np.linalg.solve(L, g + A.T @ lam))
+    K = np.block([[H, A.T], [A, np.zeros((ma, ma))]])
+    ref = np.linalg.solve(K, np.concatenate([-g, -bvec]))
+    assert np.linalg.norm(x - ref[:n]) <= 1e-12 * np.linalg.norm(ref[:n])
+    assert np.linalg.norm(lam - ref[n:]) <= 1e-12 * np.linalg.norm(ref[n:])
+
+
 # ----------------------------------------------------------------- trmm_rlnn
 
 def test_trmm_rlnn_integer_exact():
