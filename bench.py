@@ -163,6 +163,37 @@ def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
     return out
 
 
+def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
+    """The range-space method of the stacking passage on a uniform batch:
+    potrf_l_mn of [H; A] (H 40x40, 8 constraints: 48 stacked rows fill three
+    panels), then chol(Y Y^T) of the 8x40 block Y = A L^-T by the fused
+    syrk+potrf kernel."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((batch, n, n))
+    H = G @ np.swapaxes(G, 1, 2) + n * np.eye(n)
+    C = np.concatenate([H, rng.standard_normal((batch, ma, n))], axis=1)
+    sC, sD = p.pack_batch(torch.as_tensor(C, device=dev)), p.DMatBatch(batch, n + ma, n)
+    info = torch.zeros(batch, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    _, t1 = time_events(lambda: p.blasfeo_hip_dpotrf_l_mn_batched(batch, n + ma, n, sC, 0, 0, sD, 0, 0, info, stream),
+                        reps, 2, stream)
+    Y = p.unpack_batch(sD)[:, n:, :].contiguous()
+    sY, sZ = p.pack_batch(Y), p.pack_batch(torch.zeros((batch, ma, ma), dtype=torch.float64, device=dev))
+    sS = p.DMatBatch(batch, ma, ma, fill=0.0)
+    info2 = torch.zeros(batch, dtype=torch.int32, device=dev)
+    _, t2 = time_events(lambda: p.blasfeo_hip_dsyrk_dpotrf_trsm_batched(batch, ma, n, 0, sY, sZ, None, sS, None, info2,
+                                                                        stream), reps, 2, stream)
+    m1, m2 = float(np.median(t1)), float(np.median(t2))
+    fl1 = flops_potrf(n) + ma * n * n
+    fl2 = ma * (ma + 1) * n + flops_potrf(ma)
+    return {"stacked_potrf_l_mn_ms": round(m1, 4), "stacked_potrf_l_mn_gflops": round(batch * fl1 / m1 / 1e6, 1),
+            "range_space_schur_chol_ms": round(m2, 4),
+            "range_space_chain_ms": round(m1 + m2, 4),
+            "range_space_config": f"{batch} x (H {n}x{n}, A {ma}x{n})",
+            "range_space_failed": int((info != 0).sum().item() + (info2 != 0).sum().item())}
+
+
 def mixed_fp64_counts(ns, nrhs):
     """FP64 path per system: potrf n^3/3 + forward/back solves 2 n^2 per rhs."""
     ns = np.asarray(ns, dtype=np.float64)
@@ -286,8 +317,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="time only the uniform-batch workload")
-    ap.add_argument("--legs", default="uneven,riccati,mixed",
-                    help="comma list of the further workloads to time (uneven, riccati, mixed)")
+    ap.add_argument("--legs", default="uneven,riccati,stacking,mixed",
+                    help="comma list of the further workloads to time (uneven, riccati, stacking, mixed)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -357,6 +388,9 @@ def main():
     if "riccati" in legs:
         print("[bench] Riccati batch (4096 x N=20)", file=sys.stderr, flush=True)
         extra.update(bench_riccati(p, synth, torch))
+    if "stacking" in legs:
+        print("[bench] stacked potrf_l_mn + range-space chain (16384 x (40 + 8) x 40)", file=sys.stderr, flush=True)
+        extra.update(bench_stacking(p, torch))
     if "mixed" in legs:
         print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
         extra.update(bench_mixed(p, synth, torch))

@@ -160,6 +160,16 @@ void blasfeo_dtrsm_rltn(int m, int n, double alpha, struct blasfeo_dmat *sA,
 void blasfeo_dpotrf_l(int m, struct blasfeo_dmat *sC, int ci, int cj,
                       struct blasfeo_dmat *sD, int di, int dj);
 
+/* potrf_l_mn (§4.7.2, stacking matrices): for the stacked m-by-n matrix
+ * C = [H; A] (m >= n, H n-by-n SPD, lower triangle read; A (m-n)-by-n, all
+ * read) writes D = [L; A L^{-T}] with L L^T = H (the lower triangle of the
+ * top block and all of the bottom block) and sD->dA[0..n-1] = 1/diag(L):
+ * potrf_l and trsm_rltn in one sweep.  Errors: -1 m < 0, -2 n < 0 or
+ * n > m, -3 C, -6 D (or a NULL dA).  C and D may be the same matrix at the
+ * same offsets. */
+void blasfeo_dpotrf_l_mn(int m, int n, struct blasfeo_dmat *sC, int ci,
+                         int cj, struct blasfeo_dmat *sD, int di, int dj);
+
 /* syrk_potrf_ln (Appendix A.3, §4.7.2): D = chol(C + A*B^T), lower, with
  * A, B m-by-k, and sD->dA as in potrf_l; the product is never stored. */
 void blasfeo_dsyrk_dpotrf_ln(int m, int k, struct blasfeo_dmat *sA, int ai,
@@ -267,6 +277,13 @@ int blasfeo_hip_dpotrf_l_batched(int batch, int m,
                                  const struct blasfeo_dmat *sC, int ci,
                                  int cj, const struct blasfeo_dmat *sD,
                                  int di, int dj, int *info, void *stream);
+
+/* Uniform batch of potrf_l_mn; info[b] as for potrf_l (first failing pivot,
+ * 1-based, or 0).  Returns 0, -i for bad argument i, or a HIP error code. */
+int blasfeo_hip_dpotrf_l_mn_batched(int batch, int m, int n,
+                                    const struct blasfeo_dmat *sC, int ci,
+                                    int cj, const struct blasfeo_dmat *sD,
+                                    int di, int dj, int *info, void *stream);
 
 /* The range-space pair of §4.7.2 as one persistent fused kernel: per
  * instance b

@@ -167,7 +167,7 @@ struct PotrfLds {
 };
 
 __global__ __launch_bounds__(64 * GW) void k_potrf_l(
-    int m, int k, View A, View B, View C, View D, double *dA, int *info,
+    int m, int n, int k, View A, View B, View C, View D, double *dA, int *info,
     long long sA, long long sB, long long sC, long long sD, long long sdA) {
   A = at_batch(A, sA);
   B = at_batch(B, sB);
@@ -178,11 +178,11 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
   __shared__ PotrfLds s;
   const int w = wave_id();
   const int l = lane_id();
-  const int nb = (m + 15) >> 4;
+  const int nb = (n + 15) >> 4, nbr = (m + 15) >> 4;
   if (threadIdx.x == 0) s.info = 0;
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    const int nv = min(16, m - 16 * j);
+    const int nv = min(16, n - 16 * j);
     if (w == 0) {
       d4 t = load_tileT(C, 16 * j, 16 * j, true);
       for (int k0 = 0; k0 < k; k0 += 4)
@@ -191,10 +191,25 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
         const d4 u = load_tileT(D, 16 * j, 16 * q, false);  // U(q,j)
         t = mfma_tn(neg4(u), u, t);
       }
+      // stacked rows below column n that share this tile (the last block
+      // column of a non-square factorization): they are solved with the
+      // block's inverse like any off-diagonal block
+      const int l16 = l & 15, g4 = l >> 4;
+      const bool stacked = min(16, m - 16 * j) > nv;
+      d4 tb = zero4();
+      if (stacked) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tb[r] = (l16 >= nv && g4 + 4 * r < nv) ? t[r] : 0.0;
+      }
       pad_identity(t, nv);
       d4 v;
       const int inf = potrf_inv_tile_upper(t, v, s.d);
       if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
+      if (stacked) {
+        const d4 ub = mfma_tn(v, tb, zero4());
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = l16 >= nv ? ub[r] : t[r];
+      }
       store_tileT(D, 16 * j, 16 * j, t, true);
       if (dAb && l < nv) dAb[16 * j + l] = s.d.inv[l];
 #pragma unroll
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
     d4 v;
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = s.V[l * 4 + r];
-    for (int i = j + 1 + w; i < nb; i += GW) {
+    for (int i = j + 1 + w; i < nbr; i += GW) {
       d4 t = load_tileT(C, 16 * i, 16 * j, false);  // M(j,i) = C(i,j)^T
       for (int k0 = 0; k0 < k; k0 += 4)
         t = mfma(load_frag(B, 16 * j, k0), load_frag(A, 16 * i, k0), t);
@@ -230,7 +245,7 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
 // block is read and written once, with no barrier.
 template <int NB>
 __global__ __launch_bounds__(64) void k_potrf_reg(
-    int m, int k, View A, View B, View C, View D, double *dA, int *info,
+    int m, int n, int k, View A, View B, View C, View D, double *dA, int *info,
     long long sA, long long sB, long long sC, long long sD, long long sdA) {
   A = at_batch(A, sA);
   B = at_batch(B, sB);
@@ -259,15 +274,29 @@ __global__ __launch_bounds__(64) void k_potrf_reg(
       for (int j = 0; j <= i; ++j) T[tix_up(j, i)] = mfma(fb[j], fa[i], T[tix_up(j, i)]);
   }
   int inf0 = 0;
+  const int c16 = l & 15, g4 = l >> 4;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int nv = min(16, m - 16 * j);
+    const int nv = min(16, n - 16 * j);
     if (nv <= 0) break;
     d4 &Dj = T[tix_up(j, j)];
+    // stacked rows below column n inside this tile (m > n, last block
+    // column): solved with the block's inverse like an off-diagonal block
+    const bool stacked = min(16, m - 16 * j) > nv;
+    d4 tb = zero4();
+    if (stacked) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tb[r] = (c16 >= nv && g4 + 4 * r < nv) ? Dj[r] : 0.0;
+    }
     pad_identity(Dj, nv);
     d4 V;
     const int inf = potrf_inv_tile_upper(Dj, V, s);
     if (inf && inf0 == 0) inf0 = 16 * j + inf;
+    if (stacked) {
+      const d4 ub = mfma_tn(V, tb, zero4());
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Dj[r] = c16 >= nv ? ub[r] : Dj[r];
+    }
     store_tileT(D, 16 * j, 16 * j, Dj, true);
     if (dAb && l < nv) dAb[16 * j + l] = s.inv[l];
 #pragma unroll
@@ -357,9 +386,14 @@ int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
                  int aj, const blasfeo_dmat *sB, int bi, int bj,
                  const blasfeo_dmat *sC, int ci, int cj,
                  const blasfeo_dmat *sD, int di, int dj, int *info,
-                 hipStream_t st) {
+                 hipStream_t st, int n = -1) {
+  // n < 0: square (n = m); otherwise the stacked m-by-n factorization
+  // (rows m <= 64: one wave with the factor in registers; else the
+  // left-looking workgroup kernel), the same kernels in both cases
+  const bool square = n < 0 || n == m;
+  if (n < 0) n = m;
   if (batch == 0) return 0;
-  if (m == 0) {
+  if (n == 0) {
     // a fill kernel rather than a memset node, so that the call can be
     // captured into a graph
     if (info) hipLaunchKernelGGL(k_fill_int, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch, 0);
@@ -370,18 +404,19 @@ int launch_potrf(int batch, int m, int k, const blasfeo_dmat *sA, int ai,
     A = make_view(sA, ai, aj, m, k);
     B = make_view(sB, bi, bj, m, k);
   }
-  View C = make_view(sC, ci, cj, m, m);
-  View D = make_view(sD, di, dj, m, m);
+  View C = make_view(sC, ci, cj, m, n);
+  View D = make_view(sD, di, dj, m, n);
   const long long ssA = k > 0 ? batch_stride(sA) : 0, ssB = k > 0 ? batch_stride(sB) : 0;
   const long long ssC = batch_stride(sC), ssD = batch_stride(sD);
   const dim3 g(1, batch);
+  (void)square;
   switch ((m + 15) / 16) {
-    case 1: hipLaunchKernelGGL(k_potrf_reg<1>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
-    case 2: hipLaunchKernelGGL(k_potrf_reg<2>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
-    case 3: hipLaunchKernelGGL(k_potrf_reg<3>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
-    case 4: hipLaunchKernelGGL(k_potrf_reg<4>, g, dim3(64), 0, st, m, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 1: hipLaunchKernelGGL(k_potrf_reg<1>, g, dim3(64), 0, st, m, n, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 2: hipLaunchKernelGGL(k_potrf_reg<2>, g, dim3(64), 0, st, m, n, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 3: hipLaunchKernelGGL(k_potrf_reg<3>, g, dim3(64), 0, st, m, n, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
+    case 4: hipLaunchKernelGGL(k_potrf_reg<4>, g, dim3(64), 0, st, m, n, k, A, B, C, D, sD->dA, info, ssA, ssB, ssC, ssD, ssD); break;
     default:
-      hipLaunchKernelGGL(k_potrf_l, g, dim3(64 * GW), 0, st, m, k, A, B, C, D, sD->dA, info,
+      hipLaunchKernelGGL(k_potrf_l, g, dim3(64 * GW), 0, st, m, n, k, A, B, C, D, sD->dA, info,
                          ssA, ssB, ssC, ssD, ssD);
   }
   return launch_status();
@@ -466,6 +501,19 @@ void blasfeo_hip_dpotrf_l_info(int m, struct blasfeo_dmat *sC, int ci,
 void blasfeo_dpotrf_l(int m, struct blasfeo_dmat *sC, int ci, int cj,
                       struct blasfeo_dmat *sD, int di, int dj) {
   blasfeo_hip_dpotrf_l_info(m, sC, ci, cj, sD, di, dj, nullptr);
+}
+
+void blasfeo_dpotrf_l_mn(int m, int n, struct blasfeo_dmat *sC, int ci,
+                         int cj, struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (n < 0 || n > m) return set_error(-2);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
+  if (n > 0 && !sD->dA) return set_error(-6);
+  int e = launch_potrf(1, m, 0, nullptr, 0, 0, nullptr, 0, 0, sC, ci, cj, sD,
+                       di, dj, nullptr, tl_stream(), n);
+  if (e == 0) sD->use_dA = (di == 0 && dj == 0);
+  set_error(e);
 }
 
 void blasfeo_hip_dsyrk_dpotrf_ln_info(int m, int k, struct blasfeo_dmat *sA,
@@ -581,6 +629,20 @@ int blasfeo_hip_dpotrf_l_batched(int batch, int m,
   if (m > 0 && !sD->dA) return -6;
   return launch_potrf(batch, m, 0, nullptr, 0, 0, nullptr, 0, 0, sC, ci, cj,
                       sD, di, dj, info, (hipStream_t)stream);
+}
+
+int blasfeo_hip_dpotrf_l_mn_batched(int batch, int m, int n,
+                                    const struct blasfeo_dmat *sC, int ci,
+                                    int cj, const struct blasfeo_dmat *sD,
+                                    int di, int dj, int *info, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (n < 0 || n > m) return -3;
+  if (!operand_ok(sC, ci, cj, m, n)) return -4;
+  if (!operand_ok(sD, di, dj, m, n)) return -7;
+  if (n > 0 && !sD->dA) return -7;
+  return launch_potrf(batch, m, 0, nullptr, 0, 0, nullptr, 0, 0, sC, ci, cj,
+                      sD, di, dj, info, (hipStream_t)stream, n);
 }
 
 }  // extern "C"

@@ -262,6 +262,94 @@ def test_dpotrf_l(n, off):
     assert sD.s.use_dA == int(di == 0 and dj == 0)
 
 
+# ------------------------------------------------------------------ potrf_l_mn (stacking)
+
+def stacked(m, n, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    H = G @ G.T + n * np.eye(n)
+    A = rng.standard_normal((m - n, n))
+    return np.vstack([H, A])
+
+
+@pytest.mark.parametrize("m,n", [(46, 40), (20, 16), (64, 33), (100, 64), (17, 1), (130, 100), (5, 5), (33, 31)])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
+def test_dpotrf_l_mn(m, n, off):
+    """[H; A] -> [L; A L^-T] element by element against the oracle, with the
+    stacked rows sharing the last diagonal tile when n is not a multiple of
+    16 (46 x 40: rows 40..45 sit in the tile of columns 32..39); only the
+    lower part of H is read; the strictly upper part of the top block of D
+    and everything outside D keep their sentinels."""
+    note("potrf_l_mn", m, n, off)
+    ci, cj, di, dj = off
+    C = stacked(m, n, m * 7 + n)
+    Cp = C.copy()
+    Cp[:n][np.triu_indices(n, 1)] = np.nan
+    sC, sD = sentinel_mat(ci + m, cj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(Cp), sC, ci, cj)
+    p.blasfeo_dpotrf_l_mn(m, n, sC, ci, cj, sD, di, dj)
+    Dfull = host(sD)
+    D = Dfull[di:, dj:]
+    Dr, dAr, inf = oracle.dpotrf_l_mn(C, n)
+    assert inf == 0
+    low = np.tril(np.ones((m, n), bool))
+    assert_parity(np.where(low, D, 0.0), Dr, n, "potrf_l_mn")
+    assert np.all(D[~low] == SENT)
+    assert np.all(Dfull[:di] == SENT) and np.all(Dfull[:, :dj] == SENT)
+    assert_parity(sD.dA()[:n].cpu().numpy(), dAr, n, "dA")
+
+
+def test_dpotrf_l_mn_exact_and_failure():
+    note("potrf_l_mn exact")
+    for m, n, seed in ((46, 40, 60), (70, 33, 61)):
+        L, LL = synth.small_integer_factor(n, seed=seed)
+        Y = np.random.default_rng(seed).integers(-3, 4, (m - n, n)).astype(float)
+        sC, sD = mat(np.vstack([LL, Y @ L.T])), p.DMat(m, n)
+        p.blasfeo_dpotrf_l_mn(m, n, sC, 0, 0, sD, 0, 0)
+        assert np.array_equal(np.tril(host(sD)), np.vstack([L, Y]))
+    # a non-positive pivot in the last block column (which holds stacked rows)
+    C = stacked(46, 40, 62)
+    C[37, 37] = -1.0
+    batch = 3
+    sC = p.pack_batch(dev(np.stack([stacked(46, 40, 63), C, stacked(46, 40, 64)])))
+    sD = p.DMatBatch(batch, 46, 40)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_mn_batched(batch, 46, 40, sC, 0, 0, sD, 0, 0, info)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0, oracle.dpotrf_l_mn(C, 40)[2], 0] == [0, 38, 0]
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dpotrf_l_mn_batched(batch, 39, 40, sC, 0, 0, sD, 0, 0, info)
+
+
+def test_range_space_chain_batched():
+    """The two fused calls of the range-space method on a uniform batch:
+    potrf_l_mn([H; A]) = [L; Y] (n = 40, 8 constraints: 48 stacked rows fill
+    three panels, one fewer than H and A apart), then chol(Y Y^T) by the fused
+    syrk+potrf kernel; every instance's factors against the oracle chain."""
+    note("range-space chain batched")
+    batch, n, ma = 512, 40, 8
+    C = np.stack([stacked(n + ma, n, 100 + b) for b in range(batch)])
+    sC, sD = p.pack_batch(dev(C)), p.DMatBatch(batch, n + ma, n)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dpotrf_l_mn_batched(batch, n + ma, n, sC, 0, 0, sD, 0, 0, info)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    D = p.unpack_batch(sD).cpu().numpy()
+    Y = D[:, n:, :]
+    sY, sZ = p.pack_batch(dev(Y)), p.pack_batch(dev(np.zeros((batch, ma, ma))))
+    sS = p.DMatBatch(batch, ma, ma, fill=0.0)
+    info2 = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dsyrk_dpotrf_trsm_batched(batch, ma, n, 0, sY, sZ, None, sS, None, info2)
+    torch.cuda.synchronize()
+    assert int((info2 != 0).sum()) == 0
+    S = p.unpack_batch(sS).cpu().numpy()
+    for b in range(0, batch, 37):
+        Dr, _, _ = oracle.dpotrf_l_mn(C[b], n)
+        assert_parity(np.where(np.tril(np.ones((n + ma, n), bool)), D[b], 0.0), Dr, n, f"D b={b}")
+        Sr, _, _ = oracle.dsyrk_dpotrf_ln(Dr[n:], Dr[n:], np.zeros((ma, ma)))
+        assert_parity(np.tril(S[b]), Sr, n, f"S b={b}")
+
+
 @pytest.mark.parametrize("n", [16, 37, 64, 100])
 def test_dpotrf_l_small_integer_exact(n):
     note("potrf exact", n)
