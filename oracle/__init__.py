@@ -35,6 +35,7 @@ def lib():
         L = ctypes.CDLL(_build.LIB)
         L.orc_dgemm_nt.argtypes = [_i, _i, _i, _d, _dp, _i, _dp, _i, _d, _dp, _i, _dp, _i]
         L.orc_dsyrk_ln.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _d, _dp, _i, _dp, _i]
+        L.orc_dgemm_nn.argtypes = [_i, _i, _i, _d, _dp, _i, _dp, _i, _d, _dp, _i, _dp, _i]
         L.orc_dpotrf_l.argtypes = [_i, _dp, _i, _dp, _i, _dp]
         L.orc_dpotrf_l.restype = _i
         L.orc_dtrsm_rltn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
@@ -93,6 +94,17 @@ def dgemm_nt(A, B, C, alpha=1.0, beta=1.0):
     assert B.shape == (n, k) and C.shape == (m, n)
     D = np.zeros((m, n), order="F")
     lib().orc_dgemm_nt(m, n, k, alpha, _p(A), _ld(A), _p(B), _ld(B), beta, _p(C), _ld(C), _p(D), _ld(D))
+    return D
+
+
+def dgemm_nn(A, B, C, alpha=1.0, beta=1.0):
+    """D = alpha*A*B + beta*C."""
+    A, B, C = _f64(A), _f64(B), _f64(C)
+    m, k = A.shape
+    n = B.shape[1]
+    assert B.shape == (k, n) and C.shape == (m, n)
+    D = np.zeros((m, n), order="F")
+    lib().orc_dgemm_nn(m, n, k, alpha, _p(A), _ld(A), _p(B), _ld(B), beta, _p(C), _ld(C), _p(D), _ld(D))
     return D
 
 

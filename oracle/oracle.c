@@ -37,6 +37,20 @@ void orc_dgemm_nt(int m, int n, int k, double alpha, const double *A, int lda,
     }
 }
 
+/* gemm_nn, §4.4 (the NN variant of the gemm kernel: B read across panels)
+ * and §5.2.2: D <- alpha*A*B + beta*C with A m-by-k, B k-by-n, C and D
+ * m-by-n; C and D may be the same array. */
+void orc_dgemm_nn(int m, int n, int k, double alpha, const double *A, int lda,
+                  const double *B, int ldb, double beta, const double *C,
+                  int ldc, double *D, int ldd) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += EL(A, lda, i, l) * EL(B, ldb, l, j);
+      EL(D, ldd, i, j) = beta * EL(C, ldc, i, j) + alpha * s;
+    }
+}
+
 /* syrk_ln, §5.2.2 (syrk_ln paragraph): the lower triangle of
  * alpha*A*B^T + beta*C, where the two factors A and B (both m-by-k) may
  * differ.  The strictly upper part of D is neither read nor written. */

@@ -202,6 +202,22 @@ def test_potrf_info_first_failing_pivot(bad):
     assert oracle.dpotrf_l(A)[2] == bad + 1
 
 
+# ----------------------------------------------------------------- gemm_nn
+
+def test_gemm_nn_integer_exact_and_against_nt():
+    rng = np.random.default_rng(70)
+    for m, n, k in ((1, 1, 1), (7, 5, 9), (33, 17, 40)):
+        A = rng.integers(-4, 5, (m, k))
+        B = rng.integers(-4, 5, (k, n))
+        C = rng.integers(-4, 5, (m, n))
+        exact = (A.astype(np.int64) @ B.astype(np.int64)) * 3 - 2 * C.astype(np.int64)
+        D = oracle.dgemm_nn(A.astype(float), B.astype(float), C.astype(float), alpha=3.0, beta=-2.0)
+        assert np.array_equal(D, exact.astype(float))
+        # the NN product is the NT product with the transposed right factor
+        Af, Bf, Cf = (rng.uniform(-1, 1, s) for s in ((m, k), (k, n), (m, n)))
+        assert np.array_equal(oracle.dgemm_nn(Af, Bf, Cf, 0.5, 1.5), oracle.dgemm_nt(Af, Bf.T, Cf, 0.5, 1.5))
+
+
 # ----------------------------------------------------------------- potrf_l_mn (stacking)
 
 def test_potrf_l_mn_exact_stacked():
