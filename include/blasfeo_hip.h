@@ -129,6 +129,16 @@ void blasfeo_dgemm_nt(int m, int n, int k, double alpha,
                       struct blasfeo_dmat *sC, int ci, int cj,
                       struct blasfeo_dmat *sD, int di, int dj);
 
+/* gemm_nn (§4.4, the NN variant: B read across panels): D <- alpha*A*B +
+ * beta*C, A m-by-k at (ai,aj), B k-by-n at (bi,bj), C and D m-by-n.  C and
+ * D may be the same matrix at the same offsets; any other overlap of D with
+ * an input is undefined. */
+void blasfeo_dgemm_nn(int m, int n, int k, double alpha,
+                      struct blasfeo_dmat *sA, int ai, int aj,
+                      struct blasfeo_dmat *sB, int bi, int bj, double beta,
+                      struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj);
+
 /* syrk_ln (§5.2.2): lower triangle of D <- alpha*A*B^T + beta*C, A and B
  * m-by-k (they may differ), C and D m-by-m.  Only elements on or below the
  * diagonal of the D sub-matrix are written and only those of C are read. */
@@ -239,6 +249,16 @@ int blasfeo_hip_pack_dmat_indexed(int count, int m, int n, const double *A,
                                   int to_panel, void *stream);
 
 int blasfeo_hip_dgemm_nt_batched(int batch, int m, int n, int k,
+                                 double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream);
+
+/* Uniform batch of gemm_nn (same conventions as the gemm_nt batch). */
+int blasfeo_hip_dgemm_nn_batched(int batch, int m, int n, int k,
                                  double alpha,
                                  const struct blasfeo_dmat *sA, int ai,
                                  int aj, const struct blasfeo_dmat *sB,

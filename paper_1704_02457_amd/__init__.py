@@ -52,6 +52,7 @@ _SIGS = {
     "blasfeo_pack_dvec": (None, [_i, _p, _V, _i]),
     "blasfeo_unpack_dvec": (None, [_i, _V, _i, _p]),
     "blasfeo_dgemm_nt": (None, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dgemm_nn": (None, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dsyrk_ln": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dtrsm_rltn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dtrmm_rlnn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
@@ -68,6 +69,7 @@ _SIGS = {
     "blasfeo_hip_pack_dmat_batched": (_i, [_i, _i, _i, _p, _i, _ll, _M, _i, _i, _p]),
     "blasfeo_hip_unpack_dmat_batched": (_i, [_i, _i, _i, _M, _i, _i, _p, _i, _ll, _p]),
     "blasfeo_hip_dgemm_nt_batched": (_i, [_i, _i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_hip_dgemm_nn_batched": (_i, [_i, _i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dsyrk_ln_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _d, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dtrsm_rltn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dtrmm_rlnn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
@@ -277,6 +279,12 @@ def blasfeo_dgemm_nt(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, s
     check_last()
 
 
+def blasfeo_dgemm_nn(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dgemm_nn(m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
 def blasfeo_dsyrk_ln(m, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
     _sync_stream()
     lib().blasfeo_dsyrk_ln(m, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
@@ -329,6 +337,12 @@ def blasfeo_hip_dsyrk_dpotrf_ln_info(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, s
 def blasfeo_hip_dgemm_nt_batched(batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
                                  stream=None):
     return check(lib().blasfeo_hip_dgemm_nt_batched(batch, m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
+                                                    sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_dgemm_nn_batched(batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
+                                 stream=None):
+    return check(lib().blasfeo_hip_dgemm_nn_batched(batch, m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
                                                     sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
 
 

@@ -1,4 +1,4 @@
-// Generic panel-major level-3 routines: gemm_nt, syrk_ln, trmm_rlnn,
+// Generic panel-major level-3 routines: gemm_nt, gemm_nn, syrk_ln, trmm_rlnn,
 // trsm_rltn, potrf_l and syrk_potrf_ln on arbitrary sub-matrices (any (ai, aj), any
 // sizes), single instance or uniform batch (one batch index per grid row).
 //
@@ -22,7 +22,17 @@ __device__ __forceinline__ View at_batch(View v, long long stride) {
 // D^T(j,i) = sum_k B_j[:,k] A_i[:,k]^T with one MFMA per 4-wide k-step (the
 // gemm_nt k-loop of §4.4.1: both factors are read along panels), then
 // applies alpha/beta and stores with the generic masked store.
-template <bool SYRK>
+// B^T fragment read column-wise from a k-by-n B (the NN variant, §4.4: B is
+// read across panels): lane (c, g) holds B[k0 + g][j0 + c]
+__device__ __forceinline__ double load_fragT(const View &v, int j0, int k0) {
+  const int l = lane_id();
+  const int j = j0 + (l & 15), k = k0 + (l >> 4);
+  const bool ok = k < v.rows && j < v.cols;
+  const double x = v.p[ok ? pm_off(v.ai + k, v.aj + j, v.cn) : pm_off(v.ai, v.aj, v.cn)];
+  return ok ? x : 0.0;
+}
+
+template <bool SYRK, bool NN = false>
 __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
     int m, int n, int k, double alpha, View A, View B, double beta, View C,
     View D, long long sA, long long sB, long long sC, long long sD) {
@@ -47,7 +57,7 @@ __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
   }
   d4 acc = zero4();
   for (int k0 = 0; k0 < k; k0 += 4) {
-    const double fb = load_frag(B, 16 * tj, k0);
+    const double fb = NN ? load_fragT(B, 16 * tj, k0) : load_frag(B, 16 * tj, k0);
     const double fa = load_frag(A, 16 * ti, k0);
     acc = mfma(fb, fa, acc);
   }
@@ -325,16 +335,20 @@ int launch_gemm(bool syrk, int batch, int m, int n, int k, double alpha,
                 const blasfeo_dmat *sA, int ai, int aj, const blasfeo_dmat *sB,
                 int bi, int bj, double beta, const blasfeo_dmat *sC, int ci,
                 int cj, const blasfeo_dmat *sD, int di, int dj,
-                hipStream_t st) {
+                hipStream_t st, bool nn = false) {
   if (batch == 0 || m == 0 || n == 0) return 0;
   const int tm = (m + 15) / 16, tn = (n + 15) / 16;
   const int tiles = syrk ? tm * (tm + 1) / 2 : tm * tn;
   dim3 grid((tiles + GW - 1) / GW, batch);
   View A = make_view(sA, ai, aj, m, k);
-  View B = make_view(sB, bi, bj, n, k);
+  View B = nn ? make_view(sB, bi, bj, k, n) : make_view(sB, bi, bj, n, k);
   View C = make_view(sC, ci, cj, m, n);
   View D = make_view(sD, di, dj, m, n);
-  if (syrk)
+  if (nn)
+    hipLaunchKernelGGL((k_gemm_nt<false, true>), grid, dim3(64 * GW), 0, st, m, n,
+                       k, alpha, A, B, beta, C, D, batch_stride(sA),
+                       batch_stride(sB), batch_stride(sC), batch_stride(sD));
+  else if (syrk)
     hipLaunchKernelGGL(k_gemm_nt<true>, grid, dim3(64 * GW), 0, st, m, n, k,
                        alpha, A, B, beta, C, D, batch_stride(sA),
                        batch_stride(sB), batch_stride(sC), batch_stride(sD));
@@ -442,6 +456,22 @@ void blasfeo_dgemm_nt(int m, int n, int k, double alpha,
   if (!operand_ok(sD, di, dj, m, n)) return set_error(-15);
   set_error(launch_gemm(false, 1, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
                         beta, sC, ci, cj, sD, di, dj, tl_stream()));
+}
+
+void blasfeo_dgemm_nn(int m, int n, int k, double alpha,
+                      struct blasfeo_dmat *sA, int ai, int aj,
+                      struct blasfeo_dmat *sB, int bi, int bj, double beta,
+                      struct blasfeo_dmat *sC, int ci, int cj,
+                      struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0) return set_error(-1);
+  if (n < 0) return set_error(-2);
+  if (k < 0) return set_error(-3);
+  if (!operand_ok(sA, ai, aj, m, k)) return set_error(-5);
+  if (!operand_ok(sB, bi, bj, k, n)) return set_error(-8);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-12);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-15);
+  set_error(launch_gemm(false, 1, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
+                        beta, sC, ci, cj, sD, di, dj, tl_stream(), true));
 }
 
 void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
@@ -563,6 +593,26 @@ int blasfeo_hip_dgemm_nt_batched(int batch, int m, int n, int k,
   if (!operand_ok(sD, di, dj, m, n)) return -16;
   return launch_gemm(false, batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
                      beta, sC, ci, cj, sD, di, dj, (hipStream_t)stream);
+}
+
+int blasfeo_hip_dgemm_nn_batched(int batch, int m, int n, int k,
+                                 double alpha,
+                                 const struct blasfeo_dmat *sA, int ai,
+                                 int aj, const struct blasfeo_dmat *sB,
+                                 int bi, int bj, double beta,
+                                 const struct blasfeo_dmat *sC, int ci,
+                                 int cj, const struct blasfeo_dmat *sD,
+                                 int di, int dj, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (k < 0) return -4;
+  if (!operand_ok(sA, ai, aj, m, k)) return -6;
+  if (!operand_ok(sB, bi, bj, k, n)) return -9;
+  if (!operand_ok(sC, ci, cj, m, n)) return -13;
+  if (!operand_ok(sD, di, dj, m, n)) return -16;
+  return launch_gemm(false, batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
+                     beta, sC, ci, cj, sD, di, dj, (hipStream_t)stream, true);
 }
 
 int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,

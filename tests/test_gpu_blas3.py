@@ -107,6 +107,53 @@ def test_dgemm_nt_integer_exact_and_in_place():
     assert np.array_equal(host(sC), C + A @ B.T)
 
 
+@pytest.mark.parametrize("m,n,k", GEMM_CASES)
+@pytest.mark.parametrize("offs", OFFS)
+def test_dgemm_nn(m, n, k, offs):
+    """D = alpha*A*B + beta*C with B k-by-n read across panels: element-wise
+    against the oracle on the gemm_nt cases and offsets."""
+    note("gemm_nn", m, n, k, offs)
+    ai, aj, bi, bj, ci, cj, di, dj = offs
+    rng = np.random.default_rng(m + 5 * n + 11 * k)
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    C = rng.uniform(-1, 1, (m, n))
+    alpha, beta = -0.5, 2.0
+    sA = sentinel_mat(ai + m, aj + k)
+    sB = sentinel_mat(bi + k, bj + n)
+    sC = sentinel_mat(ci + m, cj + n)
+    sD = sentinel_mat(di + m, dj + n)
+    p.pack(dev(A), sA, ai, aj) if m * k else None
+    p.pack(dev(B), sB, bi, bj) if n * k else None
+    p.pack(dev(C), sC, ci, cj)
+    p.blasfeo_dgemm_nn(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj)
+    D = host(sD)
+    assert_parity(D[di:, dj:], oracle.dgemm_nn(A, B, C, alpha, beta), max(m, n, k), "gemm_nn")
+    mask = np.ones_like(D, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(D[mask] == SENT)
+
+
+def test_dgemm_nn_exact_in_place_and_batched():
+    note("gemm_nn exact/in-place/batched")
+    rng = np.random.default_rng(31)
+    A = rng.integers(-8, 9, (64, 48)).astype(float)
+    B = rng.integers(-8, 9, (48, 64)).astype(float)
+    C = rng.integers(-8, 9, (64, 64)).astype(float)
+    sA, sB, sC = mat(A), mat(B), mat(C)
+    p.blasfeo_dgemm_nn(64, 64, 48, 1.0, sA, 0, 0, sB, 0, 0, 1.0, sC, 0, 0, sC, 0, 0)  # C == D
+    assert np.array_equal(host(sC), C + A @ B)
+    batch, m, n, k = 33, 20, 36, 12
+    A, B, C = rng.uniform(-1, 1, (batch, m, k)), rng.uniform(-1, 1, (batch, k, n)), rng.uniform(-1, 1, (batch, m, n))
+    sA, sB, sC = p.pack_batch(dev(A)), p.pack_batch(dev(B)), p.pack_batch(dev(C))
+    sD = p.DMatBatch(batch, m, n)
+    p.blasfeo_hip_dgemm_nn_batched(batch, m, n, k, 2.0, sA, 0, 0, sB, 0, 0, 0.5, sC, 0, 0, sD, 0, 0)
+    torch.cuda.synchronize()
+    D = p.unpack_batch(sD).cpu().numpy()
+    for b in range(batch):
+        assert_parity(D[b], oracle.dgemm_nn(A[b], B[b], C[b], 2.0, 0.5), k, f"gemm_nn b={b}")
+
+
 def test_workload_single_gemm_then_potrf():
     """The single-instance workload: gemm_nt 64^3 then potrf_l of M M^T + 64 I."""
     note("single workload")
