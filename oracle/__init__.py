@@ -42,6 +42,8 @@ def lib():
         L.orc_dtrmm_rlnn.argtypes = [_i, _i, _d, _dp, _i, _dp, _i, _dp, _i]
         L.orc_dpotrf_l_mn.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dpotrf_l_mn.restype = _i
+        L.orc_dgetrf.argtypes = [_i, _i, _dp, _i, _dp, _i, _ip, _dp, _i]
+        L.orc_dgetrf.restype = _i
         L.orc_dsyrk_dpotrf_ln.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dsyrk_dpotrf_ln.restype = _i
         L.orc_dpotrs_l.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i]
@@ -137,6 +139,19 @@ def dpotrf_l_mn(C, n):
     dA = np.zeros(max(n, 1))
     info = lib().orc_dpotrf_l_mn(m, n, _p(C), _ld(C), _p(D), _ld(D), _p(dA))
     return D, dA[:n], info
+
+
+def dgetrf(C, pivot=True):
+    """(D, ipiv, dA, info): LU of C (L unit lower below the diagonal, U
+    upper), ipiv 0-based row interchanges, dA = 1/diag(U)."""
+    C = _f64(C)
+    m, n = C.shape
+    D = np.zeros((m, n), order="F")
+    mn = min(m, n)
+    ipiv = np.zeros(max(mn, 1), dtype=np.int32)
+    dA = np.zeros(max(mn, 1))
+    info = lib().orc_dgetrf(m, n, _p(C), _ld(C), _p(D), _ld(D), ipiv.ctypes.data_as(_ip), _p(dA), int(pivot))
+    return D, ipiv[:mn], dA[:mn], info
 
 
 def dtrmm_rlnn(A, B, alpha=1.0):

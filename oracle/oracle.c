@@ -121,6 +121,50 @@ int orc_dpotrf_l_mn(int m, int n, const double *C, int ldc, double *D,
   return 0;
 }
 
+/* getrf, §5.2.2 (getrf paragraph: LU factorization with partial pivoting;
+ * the routine list of the API names the pivot and nopivot variants): the
+ * right-looking unblocked LU of the m-by-n matrix C into D.  For
+ * k = 0..min(m,n)-1: with pivoting, p = the first row i >= k of largest
+ * |D[i][k]| and rows k and p of D are swapped (ipiv[k] = p, 0-based);
+ * without, ipiv[k] = k.  Then inv = 1/D[k][k], dA[k] = inv, the multipliers
+ * D[i][k] *= inv (i > k) and the trailing update D[i][j] -= D[i][k]*D[k][j]
+ * (i, j > k).  D holds L (unit lower, below the diagonal) and U (upper).
+ * Returns 0, or k+1 for the first k with D[k][k] == 0 after the pivoting
+ * (the factorization is still completed, as in LAPACK). */
+int orc_dgetrf(int m, int n, const double *C, int ldc, double *D, int ldd,
+               int *ipiv, double *dA, int pivot) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) EL(D, ldd, i, j) = EL(C, ldc, i, j);
+  int info = 0;
+  int mn = m < n ? m : n;
+  for (int k = 0; k < mn; ++k) {
+    int p = k;
+    if (pivot) {
+      double best = fabs(EL(D, ldd, k, k));
+      for (int i = k + 1; i < m; ++i)
+        if (fabs(EL(D, ldd, i, k)) > best) {
+          best = fabs(EL(D, ldd, i, k));
+          p = i;
+        }
+      if (p != k)
+        for (int j = 0; j < n; ++j) {
+          double t = EL(D, ldd, k, j);
+          EL(D, ldd, k, j) = EL(D, ldd, p, j);
+          EL(D, ldd, p, j) = t;
+        }
+    }
+    ipiv[k] = p;
+    double piv = EL(D, ldd, k, k);
+    if (piv == 0.0 && info == 0) info = k + 1;
+    double inv = 1.0 / piv;
+    if (dA) dA[k] = inv;
+    for (int i = k + 1; i < m; ++i) EL(D, ldd, i, k) *= inv;
+    for (int j = k + 1; j < n; ++j)
+      for (int i = k + 1; i < m; ++i) EL(D, ldd, i, j) -= EL(D, ldd, i, k) * EL(D, ldd, k, j);
+  }
+  return info;
+}
+
 /* trmm_rlnn, §5.2.2 (trmm paragraph; options right, lower, not transposed,
  * not unit) and §5.3 (the C step of the Riccati recursion):
  * D = alpha * B * A with A n-by-n lower triangular and B, D m-by-n, i.e.

@@ -218,6 +218,53 @@ def test_gemm_nn_integer_exact_and_against_nt():
         assert np.array_equal(oracle.dgemm_nn(Af, Bf, Cf, 0.5, 1.5), oracle.dgemm_nt(Af, Bf.T, Cf, 0.5, 1.5))
 
 
+# ----------------------------------------------------------------- getrf
+
+def test_getrf_matches_lapack_pivots_and_factors():
+    """Partial pivoting: the same interchanges as LAPACK's getrf (scipy's
+    lu_factor, 0-based) and the same packed L\\U, on square and
+    rectangular matrices."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(80)
+    for m, n in ((1, 1), (6, 6), (40, 40), (64, 64), (30, 17), (17, 30)):
+        C = rng.standard_normal((m, n))
+        D, ipiv, dA, info = oracle.dgetrf(C, pivot=True)
+        assert info == 0
+        lu, piv = sl.lu_factor(C)
+        assert np.array_equal(ipiv, piv[:min(m, n)])
+        assert np.linalg.norm(D - lu) <= 1e-13 * max(m, n) * np.linalg.norm(lu)
+        assert np.array_equal(dA, 1.0 / np.diag(D)[:min(m, n)])
+
+
+def test_getrf_exact_small_integers():
+    """A = L U with unit-lower integer L and integer U whose diagonal is a
+    power of two: no pivoting returns L and U exactly; with pivoting
+    P A = L' U' holds exactly for the returned factors."""
+    rng = np.random.default_rng(81)
+    for n in (5, 23, 64):
+        Lm = np.tril(rng.integers(-2, 3, (n, n)), -1) + np.eye(n)
+        U = np.triu(rng.integers(-2, 3, (n, n)), 1) + np.diag(rng.choice([1.0, 2.0, -1.0, 4.0], n))
+        A = Lm @ U
+        D, ipiv, _, info = oracle.dgetrf(A, pivot=False)
+        assert info == 0 and np.array_equal(ipiv, np.arange(n))
+        assert np.array_equal(np.tril(D, -1) + np.eye(n), Lm) and np.array_equal(np.triu(D), U)
+        D, ipiv, _, info = oracle.dgetrf(A, pivot=True)
+        PA = A.copy()
+        for k, pk in enumerate(ipiv):
+            PA[[k, pk]] = PA[[pk, k]]
+        L2, U2 = np.tril(D, -1) + np.eye(n), np.triu(D)
+        assert np.linalg.norm(L2 @ U2 - PA) <= 1e-12 * np.linalg.norm(A)
+        assert np.all(np.abs(np.tril(D, -1)) <= 1.0)  # partial pivoting bounds the multipliers
+
+
+def test_getrf_zero_pivot_info():
+    A = np.array([[0.0, 1.0], [1.0, 1.0]])
+    assert oracle.dgetrf(A, pivot=False)[3] == 1
+    D, ipiv, _, info = oracle.dgetrf(A, pivot=True)
+    assert info == 0 and list(ipiv) == [1, 1]
+    assert oracle.dgetrf(np.array([[1.0, 2.0], [2.0, 4.0]]), pivot=True)[3] == 2
+
+
 # ----------------------------------------------------------------- potrf_l_mn (stacking)
 
 def test_potrf_l_mn_exact_stacked():
