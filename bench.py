@@ -187,7 +187,19 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
     m1, m2 = float(np.median(t1)), float(np.median(t2))
     fl1 = flops_potrf(n) + ma * n * n
     fl2 = ma * (ma + 1) * n + flops_potrf(ma)
-    return {"stacked_potrf_l_mn_ms": round(m1, 4), "stacked_potrf_l_mn_gflops": round(batch * fl1 / m1 / 1e6, 1),
+    # LU with partial pivoting of 16384 independent 64 x 64 matrices
+    nl = 64
+    sG = p.pack_batch(torch.as_tensor(rng.standard_normal((batch, nl, nl)), device=dev))
+    sLU = p.DMatBatch(batch, nl, nl)
+    ipiv = torch.zeros((batch, nl), dtype=torch.int32, device=dev)
+    info3 = torch.zeros(batch, dtype=torch.int32, device=dev)
+    _, t3 = time_events(lambda: p.blasfeo_hip_dgetrf_batched(batch, nl, nl, sG, 0, 0, sLU, 0, 0, 1, ipiv, info3,
+                                                             stream), reps, 2, stream)
+    m3 = float(np.median(t3))
+    del sG, sLU
+    return {"getrf_pivot_64_batch_ms": round(m3, 4),
+            "getrf_pivot_64_batch_gflops": round(batch * (2.0 / 3.0) * nl ** 3 / m3 / 1e6, 1),
+            "stacked_potrf_l_mn_ms": round(m1, 4), "stacked_potrf_l_mn_gflops": round(batch * fl1 / m1 / 1e6, 1),
             "range_space_schur_chol_ms": round(m2, 4),
             "range_space_chain_ms": round(m1 + m2, 4),
             "range_space_config": f"{batch} x (H {n}x{n}, A {ma}x{n})",

@@ -58,6 +58,8 @@ _SIGS = {
     "blasfeo_dtrmm_rlnn": (None, [_i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dpotrf_l": (None, [_i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dpotrf_l_mn": (None, [_i, _i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dgetrf_pivot": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _p]),
+    "blasfeo_dgetrf_nopivot": (None, [_i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dsyrk_dpotrf_ln": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_hip_dpotrf_l_info": (None, [_i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dsyrk_dpotrf_ln_info": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
@@ -75,6 +77,7 @@ _SIGS = {
     "blasfeo_hip_dtrmm_rlnn_batched": (_i, [_i, _i, _i, _d, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dpotrf_l_mn_batched": (_i, [_i, _i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
+    "blasfeo_hip_dgetrf_batched": (_i, [_i, _i, _i, _M, _i, _i, _M, _i, _i, _i, _p, _p, _p]),
     "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trf_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trs_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _p, _p, _p, _p, _p, _p, _p]),
@@ -315,6 +318,18 @@ def blasfeo_dpotrf_l_mn(m, n, sC, ci, cj, sD, di, dj):
     check_last()
 
 
+def blasfeo_dgetrf_pivot(m, n, sC, ci, cj, sD, di, dj, ipiv):
+    _sync_stream()
+    lib().blasfeo_dgetrf_pivot(m, n, sC.ref, ci, cj, sD.ref, di, dj, _ptr(ipiv))
+    check_last()
+
+
+def blasfeo_dgetrf_nopivot(m, n, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dgetrf_nopivot(m, n, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
 def blasfeo_dsyrk_dpotrf_ln(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, sD, di, dj):
     _sync_stream()
     lib().blasfeo_dsyrk_dpotrf_ln(m, k, sA.ref, ai, aj, sB.ref, bi, bj, sC.ref, ci, cj, sD.ref, di, dj)
@@ -370,6 +385,11 @@ def blasfeo_hip_dpotrf_l_batched(batch, m, sC, ci, cj, sD, di, dj, info, stream=
 def blasfeo_hip_dpotrf_l_mn_batched(batch, m, n, sC, ci, cj, sD, di, dj, info, stream=None):
     return check(lib().blasfeo_hip_dpotrf_l_mn_batched(batch, m, n, sC.ref, ci, cj, sD.ref, di, dj, _ptr(info),
                                                        _stream(stream)))
+
+
+def blasfeo_hip_dgetrf_batched(batch, m, n, sC, ci, cj, sD, di, dj, pivot, ipiv, info, stream=None):
+    return check(lib().blasfeo_hip_dgetrf_batched(batch, m, n, sC.ref, ci, cj, sD.ref, di, dj, int(pivot), _ptr(ipiv),
+                                                  _ptr(info), _stream(stream)))
 
 
 def blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA, sB, sP, sF, b, r, q, x0, u, x, stream=None):

@@ -1,5 +1,6 @@
 // Generic panel-major level-3 routines: gemm_nt, gemm_nn, syrk_ln, trmm_rlnn,
-// trsm_rltn, potrf_l and syrk_potrf_ln on arbitrary sub-matrices (any (ai, aj), any
+// trsm_rltn, potrf_l, potrf_l_mn, syrk_potrf_ln and getrf on arbitrary
+// sub-matrices (any (ai, aj), any
 // sizes), single instance or uniform batch (one batch index per grid row).
 //
 // These are the "generic" kernel variant of §4.4.2: every 16x16 block is
@@ -329,6 +330,96 @@ __global__ void k_fill_int(int *p, int count, int v) {
   if (i < count) p[i] = v;
 }
 
+// ---------------------------------------------------------------- getrf
+// LU with (PIVOT) or without partial pivoting of an m-by-n matrix, m, n <=
+// 64 (§5.2.2, getrf): one wave per instance, the matrix in LDS with lane i
+// owning row i, the right-looking unblocked sweep of the oracle (pivot =
+// first row of largest magnitude by a wave argmax, rows swapped in LDS,
+// multipliers by the reciprocal, rank-1 trailing update).  Contraction into
+// fused multiply-adds is switched off so that every operation rounds as the
+// oracle's does and the pivot choices agree.
+template <bool PIVOT>
+__global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, double *dA,
+                                              int *ipiv, int *info, long long sC,
+                                              long long sD, long long sdA, long long sip) {
+#pragma clang fp contract(off)
+  __shared__ double a[64][65];
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *dAb = dA ? dA + b * sdA : nullptr;
+  int *ipb = ipiv ? ipiv + b * sip : nullptr;
+  const int l = lane_id();
+  const int lr = min(l, m - 1);
+  for (int j = 0; j < n; ++j) {
+    const double x = C.p[pm_off(C.ai + lr, C.aj + j, C.cn)];  // clamped row: no branch
+    a[l][j] = l < m ? x : 0.0;
+  }
+  wave_sync();
+  int inf = 0;
+  const int mn = min(m, n);
+  for (int k = 0; k < mn; ++k) {
+    int p = k;
+    if (PIVOT) {
+      double v = (l >= k && l < m) ? fabs(a[l][k]) : -1.0;
+      int idx = l;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double v2 = __shfl_xor(v, o);
+        const int i2 = __shfl_xor(idx, o);
+        if (v2 > v || (v2 == v && i2 < idx)) {
+          v = v2;
+          idx = i2;
+        }
+      }
+      p = __builtin_amdgcn_readfirstlane(idx);
+      if (p != k) {
+        if (l < n) {
+          const double t = a[k][l];
+          a[k][l] = a[p][l];
+          a[p][l] = t;
+        }
+        wave_sync();
+      }
+    }
+    if (ipb && l == 0) ipb[k] = p;
+    const double piv = a[k][k];
+    if (piv == 0.0 && inf == 0) inf = k + 1;
+    const double inv = 1.0 / piv;
+    if (dAb && l == 0) dAb[k] = inv;
+    if (l > k && l < m) {
+      const double mult = a[l][k] * inv;
+      a[l][k] = mult;
+      for (int j = k + 1; j < n; ++j) a[l][j] -= mult * a[k][j];
+    }
+    wave_sync();
+  }
+  if (l < m)
+    for (int j = 0; j < n; ++j) D.p[pm_off(D.ai + l, D.aj + j, D.cn)] = a[l][j];
+  if (info && l == 0) info[b] = inf;
+}
+
+int launch_getrf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj,
+                 const blasfeo_dmat *sD, int di, int dj, bool pivot, int *ipiv,
+                 int *info, hipStream_t st) {
+  if (batch == 0) return 0;
+  if (m == 0 || n == 0) {
+    if (info) hipLaunchKernelGGL(k_fill_int, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch, 0);
+    return info ? launch_status() : 0;
+  }
+  View C = make_view(sC, ci, cj, m, n);
+  View D = make_view(sD, di, dj, m, n);
+  const dim3 g(1, batch);
+  const long long sdA = batch_stride(sD), sip = m < n ? m : n;
+  if (pivot)
+    hipLaunchKernelGGL(k_getrf<true>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
+                       batch_stride(sC), batch_stride(sD), sdA, sip);
+  else
+    hipLaunchKernelGGL(k_getrf<false>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
+                       batch_stride(sC), batch_stride(sD), sdA, sip);
+  return launch_status();
+}
+
 // ---------------------------------------------------------------- launchers
 
 int launch_gemm(bool syrk, int batch, int m, int n, int k, double alpha,
@@ -474,6 +565,32 @@ void blasfeo_dgemm_nn(int m, int n, int k, double alpha,
                         beta, sC, ci, cj, sD, di, dj, tl_stream(), true));
 }
 
+void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
+                          int cj, struct blasfeo_dmat *sD, int di, int dj,
+                          int *ipiv) {
+  if (m < 0 || m > 64) return set_error(-1);
+  if (n < 0 || n > 64) return set_error(-2);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
+  if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
+  if (m > 0 && n > 0 && !ipiv) return set_error(-9);
+  const int e = launch_getrf(1, m, n, sC, ci, cj, sD, di, dj, true, ipiv, nullptr, tl_stream());
+  if (e == 0) sD->use_dA = (di == 0 && dj == 0);
+  set_error(e);
+}
+
+void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
+                            int cj, struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0 || m > 64) return set_error(-1);
+  if (n < 0 || n > 64) return set_error(-2);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
+  if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
+  const int e = launch_getrf(1, m, n, sC, ci, cj, sD, di, dj, false, nullptr, nullptr, tl_stream());
+  if (e == 0) sD->use_dA = (di == 0 && dj == 0);
+  set_error(e);
+}
+
 void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
                       int ai, int aj, struct blasfeo_dmat *sB, int bi,
                       int bj, double beta, struct blasfeo_dmat *sC, int ci,
@@ -613,6 +730,22 @@ int blasfeo_hip_dgemm_nn_batched(int batch, int m, int n, int k,
   if (!operand_ok(sD, di, dj, m, n)) return -16;
   return launch_gemm(false, batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj,
                      beta, sC, ci, cj, sD, di, dj, (hipStream_t)stream, true);
+}
+
+int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
+                               const struct blasfeo_dmat *sC, int ci, int cj,
+                               const struct blasfeo_dmat *sD, int di, int dj,
+                               int pivot, int *ipiv, int *info, void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0 || m > 64) return -2;
+  if (n < 0 || n > 64) return -3;
+  if (!operand_ok(sC, ci, cj, m, n)) return -4;
+  if (!operand_ok(sD, di, dj, m, n)) return -7;
+  if (m > 0 && n > 0 && !sD->dA) return -7;
+  if (pivot != 0 && pivot != 1) return -10;
+  if (pivot && m > 0 && n > 0 && !ipiv) return -11;
+  return launch_getrf(batch, m, n, sC, ci, cj, sD, di, dj, pivot != 0, ipiv, info,
+                      (hipStream_t)stream);
 }
 
 int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,

@@ -309,6 +309,77 @@ def test_dpotrf_l(n, off):
     assert sD.s.use_dA == int(di == 0 and dj == 0)
 
 
+# ------------------------------------------------------------------ getrf
+
+@pytest.mark.parametrize("m,n", [(1, 1), (6, 6), (40, 40), (64, 64), (30, 17), (17, 30), (64, 33)])
+@pytest.mark.parametrize("pivot", [True, False])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
+def test_dgetrf(m, n, pivot, off):
+    """LU against the oracle: the same interchanges (bit-exact) and the
+    packed L\\U element by element; dA = 1/diag(U); sentinels outside D."""
+    note("getrf", m, n, pivot, off)
+    ci, cj, di, dj = off
+    rng = np.random.default_rng(m * 3 + n + int(pivot))
+    C = rng.standard_normal((m, n))
+    if not pivot:  # diagonally dominant so that no pivoting is needed
+        C[np.arange(min(m, n)), np.arange(min(m, n))] += 2.0 * n
+    sC, sD = sentinel_mat(ci + m, cj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(C), sC, ci, cj)
+    mn = min(m, n)
+    ipiv = torch.full((mn,), -1, dtype=torch.int32, device=DEV)
+    if pivot:
+        p.blasfeo_dgetrf_pivot(m, n, sC, ci, cj, sD, di, dj, ipiv)
+    else:
+        p.blasfeo_dgetrf_nopivot(m, n, sC, ci, cj, sD, di, dj)
+    Dfull = host(sD)
+    Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=pivot)
+    assert inf == 0
+    if pivot:
+        assert np.array_equal(ipiv.cpu().numpy(), ipr)
+    assert_parity(Dfull[di:, dj:], Dr, max(m, n), "getrf")
+    assert_parity(sD.dA()[:mn].cpu().numpy(), dAr, max(m, n), "dA")
+    mask = np.ones_like(Dfull, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(Dfull[mask] == SENT)
+
+
+def test_dgetrf_exact_batched_info_and_errors():
+    note("getrf exact/batched")
+    rng = np.random.default_rng(90)
+    n = 48
+    Lm = np.tril(rng.integers(-2, 3, (n, n)), -1) + np.eye(n)
+    U = np.triu(rng.integers(-2, 3, (n, n)), 1) + np.diag(rng.choice([1.0, 2.0, -1.0, 4.0], n))
+    sC, sD = mat(Lm @ U), p.DMat(n, n)
+    p.blasfeo_dgetrf_nopivot(n, n, sC, 0, 0, sD, 0, 0)
+    D = host(sD)
+    assert np.array_equal(np.tril(D, -1) + np.eye(n), Lm) and np.array_equal(np.triu(D), U)
+    # batch: a zero pivot without pivoting, the same matrix with pivoting
+    batch, m = 256, 40
+    C = rng.standard_normal((batch, m, m))
+    C[7, 0, 0] = 0.0
+    C[7, 1:, 0] = rng.standard_normal(m - 1)
+    sC, sD = p.pack_batch(dev(C)), p.DMatBatch(batch, m, m)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    ipiv = torch.full((batch, m), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 0, None, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    assert inf[7] == 1 and oracle.dgetrf(C[7], pivot=False)[3] == 1
+    p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    D = p.unpack_batch(sD).cpu().numpy()
+    ip = ipiv.cpu().numpy()
+    for b in range(0, batch, 17):
+        Dr, ipr, _, _ = oracle.dgetrf(C[b], pivot=True)
+        assert np.array_equal(ip[b], ipr)
+        assert_parity(D[b], Dr, m, f"getrf b={b}")
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dgetrf_batched(batch, 65, 40, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, None, info)
+
+
 # ------------------------------------------------------------------ potrf_l_mn (stacking)
 
 def stacked(m, n, seed):
