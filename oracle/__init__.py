@@ -44,6 +44,7 @@ def lib():
         L.orc_dpotrf_l_mn.restype = _i
         L.orc_dgetrf.argtypes = [_i, _i, _dp, _i, _dp, _i, _ip, _dp, _i]
         L.orc_dgetrf.restype = _i
+        L.orc_dgelqf.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dsyrk_dpotrf_ln.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i, _dp, _i, _dp]
         L.orc_dsyrk_dpotrf_ln.restype = _i
         L.orc_dpotrs_l.argtypes = [_i, _i, _dp, _i, _dp, _i, _dp, _i]
@@ -152,6 +153,31 @@ def dgetrf(C, pivot=True):
     dA = np.zeros(max(mn, 1))
     info = lib().orc_dgetrf(m, n, _p(C), _ld(C), _p(D), _ld(D), ipiv.ctypes.data_as(_ip), _p(dA), int(pivot))
     return D, ipiv[:mn], dA[:mn], info
+
+
+def dgelqf(C):
+    """(D, tau): compact LQ of C (L on and below the diagonal, the
+    Householder vectors above it, v[k] = 1 implicit)."""
+    C = _f64(C)
+    m, n = C.shape
+    D = np.zeros((m, n), order="F")
+    tau = np.zeros(max(min(m, n), 1))
+    lib().orc_dgelqf(m, n, _p(C), _ld(C), _p(D), _ld(D), _p(tau))
+    return D, tau[:min(m, n)]
+
+
+def lq_q(D, tau):
+    """The n-by-n orthogonal Q = H_{k-1} ... H_0 of the compact LQ form
+    (A = L Q[:min(m,n)] with L the lower part of D)."""
+    D = np.asarray(D, dtype=np.float64)
+    n = D.shape[1]
+    Q = np.eye(n)
+    for k in range(len(tau)):
+        v = np.zeros(n)
+        v[k] = 1.0
+        v[k + 1:] = D[k, k + 1:]
+        Q = Q - tau[k] * np.outer(Q @ v, v)  # Q <- Q H_k, H_k = I - tau v v'
+    return Q.T
 
 
 def dtrmm_rlnn(A, B, alpha=1.0):

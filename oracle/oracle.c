@@ -165,6 +165,46 @@ int orc_dgetrf(int m, int n, const double *C, int ldc, double *D, int ldd,
   return info;
 }
 
+/* gelqf, §5.2.2 (gelqf paragraph: the LQ factorization by Householder
+ * reflectors, unblocked here): A = L Q.  For k = 0..min(m,n)-1 the
+ * reflector H_k = I - tau_k v v' (v[k] = 1, v[j] = 0 for j < k) annihilates
+ * D[k][k+1..n-1]: alpha = D[k][k], xn = sqrt(sum_{j>k} D[k][j]^2); if
+ * xn == 0, tau_k = 0; else beta = -sign(alpha) sqrt(alpha^2 + xn^2),
+ * tau_k = (beta - alpha)/beta, v[j] = D[k][j]/(alpha - beta) (stored in
+ * D[k][j], j > k), D[k][k] = beta.  Then every row i > k is multiplied by
+ * H_k from the right: w = D[i][k] + sum_{j>k} D[i][j] v[j],
+ * D[i][k] -= tau w, D[i][j] -= tau w v[j].  On exit L is on and below the
+ * diagonal of D, the reflectors above it (the compact form of LAPACK). */
+void orc_dgelqf(int m, int n, const double *C, int ldc, double *D, int ldd,
+                double *tau) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) EL(D, ldd, i, j) = EL(C, ldc, i, j);
+  int mn = m < n ? m : n;
+  for (int k = 0; k < mn; ++k) {
+    double alpha = EL(D, ldd, k, k);
+    double ss = 0.0;
+    for (int j = k + 1; j < n; ++j) ss += EL(D, ldd, k, j) * EL(D, ldd, k, j);
+    double xn = sqrt(ss);
+    double t = 0.0;
+    if (xn != 0.0) {
+      double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      t = (beta - alpha) / beta;
+      double sc = 1.0 / (alpha - beta);
+      for (int j = k + 1; j < n; ++j) EL(D, ldd, k, j) *= sc;
+      EL(D, ldd, k, k) = beta;
+    }
+    tau[k] = t;
+    if (t == 0.0) continue;
+    for (int i = k + 1; i < m; ++i) {
+      double w = EL(D, ldd, i, k);
+      for (int j = k + 1; j < n; ++j) w += EL(D, ldd, i, j) * EL(D, ldd, k, j);
+      w *= t;
+      EL(D, ldd, i, k) -= w;
+      for (int j = k + 1; j < n; ++j) EL(D, ldd, i, j) -= w * EL(D, ldd, k, j);
+    }
+  }
+}
+
 /* trmm_rlnn, §5.2.2 (trmm paragraph; options right, lower, not transposed,
  * not unit) and §5.3 (the C step of the Riccati recursion):
  * D = alpha * B * A with A n-by-n lower triangular and B, D m-by-n, i.e.

@@ -265,6 +265,37 @@ def test_getrf_zero_pivot_info():
     assert oracle.dgetrf(np.array([[1.0, 2.0], [2.0, 4.0]]), pivot=True)[3] == 2
 
 
+# ----------------------------------------------------------------- gelqf
+
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 5), (5, 5), (7, 4), (40, 64), (64, 64), (64, 17)])
+def test_gelqf_matches_lapack_and_reconstructs(m, n):
+    """The compact LQ form equals LAPACK's QR of A^T transposed (the same
+    reflectors: geqrf on A^T annihilates the columns that gelqf annihilates
+    in the rows of A), L Q reproduces A, Q is orthogonal."""
+    import scipy.linalg.lapack as la
+    rng = np.random.default_rng(m * 100 + n)
+    A = rng.standard_normal((m, n))
+    D, tau = oracle.dgelqf(A)
+    qr, t2, _, info = la.dgeqrf(np.asfortranarray(A.T))
+    assert info == 0
+    assert np.abs(D - qr.T).max() <= 1e-14 * max(m, n) * np.abs(qr).max()
+    assert np.abs(tau - t2[:min(m, n)]).max() <= 1e-14 * max(m, n)
+    Q = oracle.lq_q(D, tau)
+    k = min(m, n)
+    assert np.abs(np.tril(D)[:, :k] @ Q[:k] - A).max() <= 1e-14 * max(m, n) * np.abs(A).max()
+    assert np.abs(Q @ Q.T - np.eye(n)).max() <= 1e-14 * n
+
+
+def test_gelqf_special_cases():
+    # a row already zero to the right of the diagonal gives tau = 0 (H = I)
+    A = np.array([[3.0, 0.0, 0.0], [1.0, 2.0, 2.0]])
+    D, tau = oracle.dgelqf(A)
+    assert tau[0] == 0.0 and D[0, 0] == 3.0
+    # a 3-4-5 row: beta = -5, tau = 8/5, v = [1, 1/2]
+    D, tau = oracle.dgelqf(np.array([[3.0, 4.0]]))
+    assert D[0, 0] == -5.0 and tau[0] == 1.6 and D[0, 1] == 0.5
+
+
 # ----------------------------------------------------------------- potrf_l_mn (stacking)
 
 def test_potrf_l_mn_exact_stacked():
