@@ -196,8 +196,15 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
     _, t3 = time_events(lambda: p.blasfeo_hip_dgetrf_batched(batch, nl, nl, sG, 0, 0, sLU, 0, 0, 1, ipiv, info3,
                                                              stream), reps, 2, stream)
     m3 = float(np.median(t3))
-    del sG, sLU
-    return {"getrf_pivot_64_batch_ms": round(m3, 4),
+    # LQ of the same matrices
+    sLQ = p.DMatBatch(batch, nl, nl)
+    _, t4 = time_events(lambda: p.blasfeo_hip_dgelqf_batched(batch, nl, nl, sG, 0, 0, sLQ, 0, 0, stream), reps, 2,
+                        stream)
+    m4 = float(np.median(t4))
+    del sG, sLU, sLQ
+    return {"gelqf_64_batch_ms": round(m4, 4),
+            "gelqf_64_batch_gflops": round(batch * (4.0 / 3.0) * nl ** 3 / m4 / 1e6, 1),
+            "getrf_pivot_64_batch_ms": round(m3, 4),
             "getrf_pivot_64_batch_gflops": round(batch * (2.0 / 3.0) * nl ** 3 / m3 / 1e6, 1),
             "stacked_potrf_l_mn_ms": round(m1, 4), "stacked_potrf_l_mn_gflops": round(batch * fl1 / m1 / 1e6, 1),
             "range_space_schur_chol_ms": round(m2, 4),

@@ -195,6 +195,16 @@ void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
 void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
                             int cj, struct blasfeo_dmat *sD, int di, int dj);
 
+/* gelqf (§5.2.2; unblocked): LQ factorization C = L Q of the m-by-n matrix
+ * C (m, n <= 64) by Householder reflectors, in LAPACK's compact form: L on
+ * and below the diagonal of D, reflector k's vector to the right of the
+ * diagonal of row k (its k-th entry 1 implicit), tau_k in sD->dA[k]
+ * (min(m,n) entries); Q = H_{min-1} ... H_0 with H_k = I - tau_k v v'.
+ * Errors: -1 m, -2 n (outside 0..64), -3 C, -6 D (or a NULL dA).  C and D
+ * may be the same matrix at the same offsets. */
+void blasfeo_dgelqf(int m, int n, struct blasfeo_dmat *sC, int ci, int cj,
+                    struct blasfeo_dmat *sD, int di, int dj);
+
 /* syrk_potrf_ln (Appendix A.3, §4.7.2): D = chol(C + A*B^T), lower, with
  * A, B m-by-k, and sD->dA as in potrf_l; the product is never stored. */
 void blasfeo_dsyrk_dpotrf_ln(int m, int k, struct blasfeo_dmat *sA, int ai,
@@ -290,6 +300,13 @@ int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sC, int ci, int cj,
                                const struct blasfeo_dmat *sD, int di, int dj,
                                int pivot, int *ipiv, int *info, void *stream);
+
+/* Uniform batch of gelqf (tau of instance b in its D's dA).  Returns 0,
+ * -i for bad argument i, or a HIP error code. */
+int blasfeo_hip_dgelqf_batched(int batch, int m, int n,
+                               const struct blasfeo_dmat *sC, int ci, int cj,
+                               const struct blasfeo_dmat *sD, int di, int dj,
+                               void *stream);
 
 int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,
                                  const struct blasfeo_dmat *sA, int ai,

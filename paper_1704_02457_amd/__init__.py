@@ -60,6 +60,7 @@ _SIGS = {
     "blasfeo_dpotrf_l_mn": (None, [_i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dgetrf_pivot": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_dgetrf_nopivot": (None, [_i, _i, _M, _i, _i, _M, _i, _i]),
+    "blasfeo_dgelqf": (None, [_i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_dsyrk_dpotrf_ln": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i]),
     "blasfeo_hip_dpotrf_l_info": (None, [_i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dsyrk_dpotrf_ln_info": (None, [_i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
@@ -78,6 +79,7 @@ _SIGS = {
     "blasfeo_hip_dpotrf_l_batched": (_i, [_i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dpotrf_l_mn_batched": (_i, [_i, _i, _i, _M, _i, _i, _M, _i, _i, _p, _p]),
     "blasfeo_hip_dgetrf_batched": (_i, [_i, _i, _i, _M, _i, _i, _M, _i, _i, _i, _p, _p, _p]),
+    "blasfeo_hip_dgelqf_batched": (_i, [_i, _i, _i, _M, _i, _i, _M, _i, _i, _p]),
     "blasfeo_hip_dsyrk_dpotrf_trsm_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trf_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trs_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _p, _p, _p, _p, _p, _p, _p]),
@@ -330,6 +332,12 @@ def blasfeo_dgetrf_nopivot(m, n, sC, ci, cj, sD, di, dj):
     check_last()
 
 
+def blasfeo_dgelqf(m, n, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_dgelqf(m, n, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
 def blasfeo_dsyrk_dpotrf_ln(m, k, sA, ai, aj, sB, bi, bj, sC, ci, cj, sD, di, dj):
     _sync_stream()
     lib().blasfeo_dsyrk_dpotrf_ln(m, k, sA.ref, ai, aj, sB.ref, bi, bj, sC.ref, ci, cj, sD.ref, di, dj)
@@ -390,6 +398,10 @@ def blasfeo_hip_dpotrf_l_mn_batched(batch, m, n, sC, ci, cj, sD, di, dj, info, s
 def blasfeo_hip_dgetrf_batched(batch, m, n, sC, ci, cj, sD, di, dj, pivot, ipiv, info, stream=None):
     return check(lib().blasfeo_hip_dgetrf_batched(batch, m, n, sC.ref, ci, cj, sD.ref, di, dj, int(pivot), _ptr(ipiv),
                                                   _ptr(info), _stream(stream)))
+
+
+def blasfeo_hip_dgelqf_batched(batch, m, n, sC, ci, cj, sD, di, dj, stream=None):
+    return check(lib().blasfeo_hip_dgelqf_batched(batch, m, n, sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
 
 
 def blasfeo_hip_dric_trs_batched(batch, nx, nu, N, sA, sB, sP, sF, b, r, q, x0, u, x, stream=None):

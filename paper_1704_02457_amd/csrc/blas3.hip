@@ -1,6 +1,6 @@
 // Generic panel-major level-3 routines: gemm_nt, gemm_nn, syrk_ln, trmm_rlnn,
-// trsm_rltn, potrf_l, potrf_l_mn, syrk_potrf_ln and getrf on arbitrary
-// sub-matrices (any (ai, aj), any
+// trsm_rltn, potrf_l, potrf_l_mn, syrk_potrf_ln, getrf and gelqf on
+// arbitrary sub-matrices (any (ai, aj), any
 // sizes), single instance or uniform batch (one batch index per grid row).
 //
 // These are the "generic" kernel variant of §4.4.2: every 16x16 block is
@@ -399,6 +399,69 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   if (info && l == 0) info[b] = inf;
 }
 
+// ---------------------------------------------------------------- gelqf
+// LQ factorization by Householder reflectors of an m-by-n matrix, m, n <= 64
+// (§5.2.2, gelqf; unblocked): one wave per instance, the matrix in LDS with
+// lane i owning row i.  Row k's reflector: the squared norm of its part right
+// of the diagonal by a wave sum, the scalars of the oracle, the vector
+// scaled in place; then every row below forms its product with the
+// reflector and subtracts.  tau goes to dA.  Contraction is off, as in the
+// oracle; only the order of the norm's sum differs.
+__global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, double *tau,
+                                              long long sC, long long sD, long long stau) {
+#pragma clang fp contract(off)
+  __shared__ double a[64][65];
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *taub = tau + b * stau;
+  const int l = lane_id();
+  const int lr = min(l, m - 1);
+  for (int j = 0; j < n; ++j) {
+    const double x = C.p[pm_off(C.ai + lr, C.aj + j, C.cn)];
+    a[l][j] = l < m ? x : 0.0;
+  }
+  wave_sync();
+  const int mn = min(m, n);
+  for (int k = 0; k < mn; ++k) {
+    const double alpha = a[k][k];
+    double sq = (l > k && l < n) ? a[k][l] * a[k][l] : 0.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o);
+    double t = 0.0;
+    if (sq != 0.0) {
+      const double beta = -copysign(sqrt(alpha * alpha + sq), alpha);
+      t = (beta - alpha) / beta;
+      const double sc = 1.0 / (alpha - beta);
+      wave_sync();
+      if (l > k && l < n) a[k][l] *= sc;
+      if (l == 0) a[k][k] = beta;
+    }
+    if (l == 0) taub[k] = t;
+    wave_sync();
+    if (t != 0.0 && l > k && l < m) {
+      double w = a[l][k];
+      for (int j = k + 1; j < n; ++j) w += a[l][j] * a[k][j];
+      w *= t;
+      a[l][k] -= w;
+      for (int j = k + 1; j < n; ++j) a[l][j] -= w * a[k][j];
+    }
+    wave_sync();
+  }
+  if (l < m)
+    for (int j = 0; j < n; ++j) D.p[pm_off(D.ai + l, D.aj + j, D.cn)] = a[l][j];
+}
+
+int launch_gelqf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj,
+                 const blasfeo_dmat *sD, int di, int dj, hipStream_t st) {
+  if (batch == 0 || m == 0 || n == 0) return 0;
+  View C = make_view(sC, ci, cj, m, n);
+  View D = make_view(sD, di, dj, m, n);
+  hipLaunchKernelGGL(k_gelqf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
+                     batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  return launch_status();
+}
+
 int launch_getrf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj,
                  const blasfeo_dmat *sD, int di, int dj, bool pivot, int *ipiv,
                  int *info, hipStream_t st) {
@@ -591,6 +654,16 @@ void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
   set_error(e);
 }
 
+void blasfeo_dgelqf(int m, int n, struct blasfeo_dmat *sC, int ci, int cj,
+                    struct blasfeo_dmat *sD, int di, int dj) {
+  if (m < 0 || m > 64) return set_error(-1);
+  if (n < 0 || n > 64) return set_error(-2);
+  if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
+  if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
+  if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
+  set_error(launch_gelqf(1, m, n, sC, ci, cj, sD, di, dj, tl_stream()));
+}
+
 void blasfeo_dsyrk_ln(int m, int k, double alpha, struct blasfeo_dmat *sA,
                       int ai, int aj, struct blasfeo_dmat *sB, int bi,
                       int bj, double beta, struct blasfeo_dmat *sC, int ci,
@@ -746,6 +819,19 @@ int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
   if (pivot && m > 0 && n > 0 && !ipiv) return -11;
   return launch_getrf(batch, m, n, sC, ci, cj, sD, di, dj, pivot != 0, ipiv, info,
                       (hipStream_t)stream);
+}
+
+int blasfeo_hip_dgelqf_batched(int batch, int m, int n,
+                               const struct blasfeo_dmat *sC, int ci, int cj,
+                               const struct blasfeo_dmat *sD, int di, int dj,
+                               void *stream) {
+  if (batch < 0 || batch > 65535) return -1;
+  if (m < 0 || m > 64) return -2;
+  if (n < 0 || n > 64) return -3;
+  if (!operand_ok(sC, ci, cj, m, n)) return -4;
+  if (!operand_ok(sD, di, dj, m, n)) return -7;
+  if (m > 0 && n > 0 && !sD->dA) return -7;
+  return launch_gelqf(batch, m, n, sC, ci, cj, sD, di, dj, (hipStream_t)stream);
 }
 
 int blasfeo_hip_dsyrk_ln_batched(int batch, int m, int k, double alpha,

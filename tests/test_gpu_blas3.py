@@ -380,6 +380,53 @@ def test_dgetrf_exact_batched_info_and_errors():
         p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, None, info)
 
 
+# ------------------------------------------------------------------ gelqf
+
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 5), (5, 5), (7, 4), (40, 64), (64, 64), (64, 17)])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
+def test_dgelqf(m, n, off):
+    """Compact LQ against the oracle element by element (reflectors and L)
+    and tau; the GPU's own factors reproduce A with an orthogonal Q."""
+    note("gelqf", m, n, off)
+    ci, cj, di, dj = off
+    A = np.random.default_rng(m * 9 + n).standard_normal((m, n))
+    sC, sD = sentinel_mat(ci + m, cj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(A), sC, ci, cj)
+    p.blasfeo_dgelqf(m, n, sC, ci, cj, sD, di, dj)
+    Dfull = host(sD)
+    D = Dfull[di:, dj:]
+    tau = sD.dA()[:min(m, n)].cpu().numpy()
+    Dr, taur = oracle.dgelqf(A)
+    assert_parity(D, Dr, max(m, n), "gelqf")
+    assert_parity(tau, taur, max(m, n), "tau")
+    Q = oracle.lq_q(D, tau)
+    k = min(m, n)
+    assert np.abs(np.tril(D)[:, :k] @ Q[:k] - A).max() <= 1e-13 * max(m, n)
+    mask = np.ones_like(Dfull, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(Dfull[mask] == SENT)
+
+
+def test_dgelqf_batched_and_zero_row():
+    note("gelqf batched")
+    rng = np.random.default_rng(91)
+    batch, m, n = 300, 24, 40
+    A = rng.standard_normal((batch, m, n))
+    A[5, 0, 1:] = 0.0  # reflector 0 of instance 5 is the identity
+    sC, sD = p.pack_batch(dev(A)), p.DMatBatch(batch, m, n)
+    p.blasfeo_hip_dgelqf_batched(batch, m, n, sC, 0, 0, sD, 0, 0)
+    torch.cuda.synchronize()
+    D = p.unpack_batch(sD).cpu().numpy()
+    tau = sD.dA()[:, :m].cpu().numpy()
+    assert tau[5, 0] == 0.0
+    for b in list(range(0, batch, 23)) + [5]:
+        Dr, taur = oracle.dgelqf(A[b])
+        assert_parity(D[b], Dr, n, f"gelqf b={b}")
+        assert_parity(tau[b], taur, n, f"tau b={b}")
+    with pytest.raises(p.HipError):
+        p.blasfeo_hip_dgelqf_batched(batch, 65, n, sC, 0, 0, sD, 0, 0)
+
+
 # ------------------------------------------------------------------ potrf_l_mn (stacking)
 
 def stacked(m, n, seed):
