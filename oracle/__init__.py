@@ -57,6 +57,8 @@ def lib():
         L.orc_spotrf_l.argtypes = [_i, _fp, _i, _fp, _i]
         L.orc_spotrf_l.restype = _i
         L.orc_spotrs_l.argtypes = [_i, _fp, _i, _fp, _fp]
+        L.orc_sgemm_nt.argtypes = [_i, _i, _i, ctypes.c_float, _fp, _i, _fp, _i, ctypes.c_float, _fp, _i, _fp, _i]
+        L.orc_ssyrk_ln.argtypes = [_i, _i, ctypes.c_float, _fp, _i, _fp, _i, ctypes.c_float, _fp, _i, _fp, _i]
         L.orc_dposv_mixed.argtypes = [_i, _dp, _i, _dp, _d, _i, _i, _dp, _dp]
         L.orc_dposv_mixed.restype = _i
         L.orc_fl16.argtypes = [ctypes.c_float]
@@ -271,6 +273,31 @@ def spotrf_l(C):
     D = np.zeros((m, m), dtype=np.float32, order="F")
     info = lib().orc_spotrf_l(m, C.ctypes.data_as(_fp), max(1, m), D.ctypes.data_as(_fp), max(1, m))
     return D, info
+
+
+def _f32(a):
+    return np.asfortranarray(np.asarray(a, dtype=np.float32))
+
+
+def sgemm_nt(A, B, C, alpha=1.0, beta=1.0):
+    """Single precision D = alpha*A*B^T + beta*C."""
+    A, B, C = _f32(A), _f32(B), _f32(C)
+    m, k = A.shape
+    n = B.shape[0]
+    D = np.zeros((m, n), dtype=np.float32, order="F")
+    fp = lambda x: x.ctypes.data_as(_fp)  # noqa: E731
+    lib().orc_sgemm_nt(m, n, k, alpha, fp(A), max(1, m), fp(B), max(1, n), beta, fp(C), max(1, m), fp(D), max(1, m))
+    return D
+
+
+def ssyrk_ln(A, B, C, alpha=1.0, beta=1.0):
+    """Single precision lower(alpha*A*B^T + beta*C); the strictly upper part is 0."""
+    A, B, C = _f32(A), _f32(B), _f32(C)
+    m, k = A.shape
+    D = np.zeros((m, m), dtype=np.float32, order="F")
+    fp = lambda x: x.ctypes.data_as(_fp)  # noqa: E731
+    lib().orc_ssyrk_ln(m, k, alpha, fp(A), max(1, m), fp(B), max(1, m), beta, fp(C), max(1, m), fp(D), max(1, m))
+    return D
 
 
 FP32, FP16_SCALED = 1, 2

@@ -498,6 +498,31 @@ int orc_spotrf_l(int m, const float *C, int ldc, float *D, int ldd) {
   return 0;
 }
 
+/* sgemm_nt and ssyrk_ln in IEEE single precision (§5.2.2: the routines
+ * come in single- and double-precision variants): the definitions of
+ * orc_dgemm_nt / orc_dsyrk_ln with every operation in float. */
+void orc_sgemm_nt(int m, int n, int k, float alpha, const float *A, int lda,
+                  const float *B, int ldb, float beta, const float *C,
+                  int ldc, float *D, int ldd) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) {
+      float s = 0.0f;
+      for (int l = 0; l < k; ++l) s += EL(A, lda, i, l) * EL(B, ldb, j, l);
+      EL(D, ldd, i, j) = beta * EL(C, ldc, i, j) + alpha * s;
+    }
+}
+
+void orc_ssyrk_ln(int m, int k, float alpha, const float *A, int lda,
+                  const float *B, int ldb, float beta, const float *C,
+                  int ldc, float *D, int ldd) {
+  for (int j = 0; j < m; ++j)
+    for (int i = j; i < m; ++i) {
+      float s = 0.0f;
+      for (int l = 0; l < k; ++l) s += EL(A, lda, i, l) * EL(B, ldb, j, l);
+      EL(D, ldd, i, j) = beta * EL(C, ldc, i, j) + alpha * s;
+    }
+}
+
 void orc_spotrs_l(int n, const float *L, int ldl, const float *b, float *x) {
   for (int i = 0; i < n; ++i) {
     float s = b[i];

@@ -616,6 +616,23 @@ def test_riccati_matches_classical_form():
 
 # ----------------------------------------------------------------- mixed precision
 
+def test_single_precision_gemm_syrk_pins():
+    """Small integers are exact in float: sgemm_nt and ssyrk_ln equal the
+    int64 products; on general data they are the double-precision routines'
+    results rounded step by step (within n float ulps)."""
+    rng = np.random.default_rng(95)
+    A, B, C = (rng.integers(-4, 5, s) for s in ((9, 7), (5, 7), (9, 5)))
+    exact = 2 * (A.astype(np.int64) @ B.T.astype(np.int64)) - C
+    assert np.array_equal(oracle.sgemm_nt(A, B, C, 2.0, -1.0), exact.astype(np.float32))
+    S = rng.integers(-4, 5, (9, 9))
+    ex = np.tril(A.astype(np.int64) @ A.T.astype(np.int64) + S)
+    assert np.array_equal(oracle.ssyrk_ln(A, A, S), ex.astype(np.float32))
+    Af, Bf, Cf = (rng.uniform(-1, 1, s) for s in ((20, 30), (11, 30), (20, 11)))
+    D32 = oracle.sgemm_nt(Af, Bf, Cf, 0.5, 1.5).astype(np.float64)
+    D64 = oracle.dgemm_nt(Af.astype(np.float32), Bf.astype(np.float32), Cf.astype(np.float32), 0.5, 1.5)
+    assert np.abs(D32 - D64).max() <= 30 * 2 ** -24 * (1 + np.abs(D64).max())
+
+
 def test_spotrf_small_integer_exact_in_fp32():
     L, A = synth.small_integer_factor(24, seed=22)
     D, info = oracle.spotrf_l(A.astype(np.float32))
