@@ -213,6 +213,32 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
             "range_space_failed": int((info != 0).sum().item() + (info2 != 0).sum().item())}
 
 
+def bench_single(p, torch, batch=16384, n=64, reps=10):
+    """The single-precision routines on 16384 independent 64 x 64 operands:
+    sgemm_nt (64x64x64) and spotrf_l of SPD matrices, FP32 panel-major."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(14)
+    f = dict(device=dev, dtype=torch.float32, generator=g)
+    A, B, C = (torch.rand((batch, n, n), **f) * 2 - 1 for _ in range(3))
+    sA, sB, sC = p.spack_batch(A), p.spack_batch(B), p.spack_batch(C)
+    sD = p.SMatBatch(batch, n, n)
+    stream = torch.cuda.current_stream()
+    _, t1 = time_events(lambda: p.blasfeo_hip_sgemm_nt_batched(batch, n, n, n, 1.0, sA, 0, 0, sB, 0, 0, 1.0, sC, 0, 0,
+                                                               sD, 0, 0, stream), reps, 2, stream)
+    S = torch.bmm(A, A.transpose(1, 2).contiguous()) / n + torch.eye(n, device=dev, dtype=torch.float32)
+    sS, sL = p.spack_batch(S), p.SMatBatch(batch, n, n)
+    info = torch.zeros(batch, dtype=torch.int32, device=dev)
+    _, t2 = time_events(lambda: p.blasfeo_hip_spotrf_l_batched(batch, n, sS, 0, 0, sL, 0, 0, info, stream), reps, 2,
+                        stream)
+    m1, m2 = float(np.median(t1)), float(np.median(t2))
+    del A, B, C, S, sA, sB, sC, sD, sS, sL
+    return {"sgemm_nt_64_batch_ms": round(m1, 4), "sgemm_nt_64_batch_gflops": round(batch * 2.0 * n ** 3 / m1 / 1e6, 1),
+            "spotrf_l_64_batch_ms": round(m2, 4),
+            "spotrf_l_64_batch_gflops": round(batch * flops_potrf(n) / m2 / 1e6, 1),
+            "spotrf_l_failed": int((info != 0).sum().item())}
+
+
 def mixed_fp64_counts(ns, nrhs):
     """FP64 path per system: potrf n^3/3 + forward/back solves 2 n^2 per rhs."""
     ns = np.asarray(ns, dtype=np.float64)
@@ -336,7 +362,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="time only the uniform-batch workload")
-    ap.add_argument("--legs", default="uneven,riccati,stacking,mixed",
+    ap.add_argument("--legs", default="uneven,riccati,stacking,single,mixed",
                     help="comma list of the further workloads to time (uneven, riccati, stacking, mixed)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -410,6 +436,9 @@ def main():
     if "stacking" in legs:
         print("[bench] stacked potrf_l_mn + range-space chain (16384 x (40 + 8) x 40)", file=sys.stderr, flush=True)
         extra.update(bench_stacking(p, torch))
+    if "single" in legs:
+        print("[bench] single precision sgemm_nt / spotrf_l (16384 x 64)", file=sys.stderr, flush=True)
+        extra.update(bench_single(p, torch))
     if "mixed" in legs:
         print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
         extra.update(bench_mixed(p, synth, torch))

@@ -409,6 +409,94 @@ int blasfeo_hip_dric_trs_batched(int batch, int nx, int nu, int N,
                                  double *u, double *x, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Single precision (Appendix A.3 lists every routine in single and double
+ * precision; §4.8 sizes the panel per precision so that a panel column fills
+ * a cache line).  struct blasfeo_smat has the members of blasfeo_dmat with
+ * float pointers; its panels hold BLASFEO_HIP_PS_S = 32 rows, so element
+ * (i, j) is at pA[(i - i % 32) * cn + j * 32 + i % 32], cn = round_up(n, 4),
+ * and a panel column is again one 128-byte line.  dA holds max(m, n)
+ * floats after the panels; memsize is a multiple of 256 bytes.
+ * The routines have the arguments, operand rules, error codes and
+ * asynchronous behaviour of their double-precision namesakes; alpha and
+ * beta are float.  Products accumulate in FP32 on the matrix cores; the
+ * 16x16 diagonal blocks of spotrf_l are factored in FP64 and rounded, so
+ * L and dA agree with an all-FP32 factorization to FP32 rounding error.
+ * ---------------------------------------------------------------------- */
+#define BLASFEO_HIP_PS_S 32
+
+struct blasfeo_smat {
+  float *pA;
+  float *dA;
+  int m;
+  int n;
+  int pm;
+  int cn;
+  int use_dA;
+  int memsize;
+};
+
+/* Bytes for an m-by-n single-precision matrix (-1 for a bad size). */
+int blasfeo_memsize_smat(int m, int n);
+void blasfeo_create_smat(int m, int n, struct blasfeo_smat *sA, void *memory);
+void blasfeo_allocate_smat(int m, int n, struct blasfeo_smat *sA);
+void blasfeo_free_smat(struct blasfeo_smat *sA);
+/* As blasfeo_pack_dmat / blasfeo_unpack_dmat (A, B float device arrays). */
+void blasfeo_pack_smat(int m, int n, const float *A, int lda,
+                       struct blasfeo_smat *sB, int bi, int bj);
+void blasfeo_unpack_smat(int m, int n, struct blasfeo_smat *sA, int ai,
+                         int aj, float *B, int ldb);
+/* As the dmat batched pack / unpack; strides in floats. */
+int blasfeo_hip_pack_smat_batched(int batch, int m, int n, const float *A,
+                                  int lda, long long strideA,
+                                  const struct blasfeo_smat *sB, int bi,
+                                  int bj, void *stream);
+int blasfeo_hip_unpack_smat_batched(int batch, int m, int n,
+                                    const struct blasfeo_smat *sA, int ai,
+                                    int aj, float *B, int ldb,
+                                    long long strideB, void *stream);
+
+/* sgemm_nt: D <- alpha*A*B^T + beta*C (as dgemm_nt; errors -1 m, -2 n,
+ * -3 k, -5 A, -8 B, -12 C, -15 D through blasfeo_hip_get_last_error). */
+void blasfeo_sgemm_nt(int m, int n, int k, float alpha,
+                      struct blasfeo_smat *sA, int ai, int aj,
+                      struct blasfeo_smat *sB, int bi, int bj, float beta,
+                      struct blasfeo_smat *sC, int ci, int cj,
+                      struct blasfeo_smat *sD, int di, int dj);
+/* ssyrk_ln: lower triangle of D <- alpha*A*B^T + beta*C, A, B m-by-k; the
+ * strictly upper part of D is not written (errors -1 m, -2 k, -4 A, -7 B,
+ * -11 C, -14 D). */
+void blasfeo_ssyrk_ln(int m, int k, float alpha, struct blasfeo_smat *sA,
+                      int ai, int aj, struct blasfeo_smat *sB, int bi,
+                      int bj, float beta, struct blasfeo_smat *sC, int ci,
+                      int cj, struct blasfeo_smat *sD, int di, int dj);
+/* spotrf_l: lower Cholesky factor D of the m-by-m SPD matrix C (lower
+ * triangle read, strictly upper part of D not written), sD->dA[i] =
+ * 1/D[i][i] (errors -1 m, -2 C, -5 D or a NULL dA).  A pivot that is not
+ * positive leaves the factor unspecified from that column on. */
+void blasfeo_spotrf_l(int m, struct blasfeo_smat *sC, int ci, int cj,
+                      struct blasfeo_smat *sD, int di, int dj);
+/* Uniform batches (instance b at b*memsize bytes; batch <= 65535).  Error
+ * codes are those of the single-instance routine shifted by one (argument
+ * i of the batched call is -i), -1 for a bad batch.  info (device, batch
+ * ints, may be NULL) receives 0 or the first failing pivot (1-based). */
+int blasfeo_hip_sgemm_nt_batched(int batch, int m, int n, int k, float alpha,
+                                 const struct blasfeo_smat *sA, int ai, int aj,
+                                 const struct blasfeo_smat *sB, int bi, int bj,
+                                 float beta, const struct blasfeo_smat *sC,
+                                 int ci, int cj, const struct blasfeo_smat *sD,
+                                 int di, int dj, void *stream);
+int blasfeo_hip_ssyrk_ln_batched(int batch, int m, int k, float alpha,
+                                 const struct blasfeo_smat *sA, int ai, int aj,
+                                 const struct blasfeo_smat *sB, int bi, int bj,
+                                 float beta, const struct blasfeo_smat *sC,
+                                 int ci, int cj, const struct blasfeo_smat *sD,
+                                 int di, int dj, void *stream);
+int blasfeo_hip_spotrf_l_batched(int batch, int m,
+                                 const struct blasfeo_smat *sC, int ci, int cj,
+                                 const struct blasfeo_smat *sD, int di, int dj,
+                                 int *info, void *stream);
+
+/* ------------------------------------------------------------------------
  * Uneven batches: plans.  A plan is created once for a list of orders and
  * executed many times (the embedded-optimization pattern of §2: the same
  * structure is re-solved at every sampling time).

@@ -498,7 +498,7 @@ int orc_spotrf_l(int m, const float *C, int ldc, float *D, int ldd) {
   return 0;
 }
 
-/* sgemm_nt and ssyrk_ln in IEEE single precision (§5.2.2: the routines
+/* sgemm_nt and ssyrk_ln in IEEE single precision (Appendix A.3: the routines
  * come in single- and double-precision variants): the definitions of
  * orc_dgemm_nt / orc_dsyrk_ln with every operation in float. */
 void orc_sgemm_nt(int m, int n, int k, float alpha, const float *A, int lda,

@@ -33,9 +33,17 @@ class blasfeo_dvec(ctypes.Structure):
                 ("memsize", ctypes.c_int)]
 
 
+class blasfeo_smat(ctypes.Structure):
+    _fields_ = [("pA", ctypes.c_void_p), ("dA", ctypes.c_void_p), ("m", ctypes.c_int),
+                ("n", ctypes.c_int), ("pm", ctypes.c_int), ("cn", ctypes.c_int),
+                ("use_dA", ctypes.c_int), ("memsize", ctypes.c_int)]
+
+
 _M = ctypes.POINTER(blasfeo_dmat)
+_S = ctypes.POINTER(blasfeo_smat)
 _V = ctypes.POINTER(blasfeo_dvec)
 _i, _d, _p, _ll = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
+_f = ctypes.c_float
 
 # name -> (restype, argtypes)
 _SIGS = {
@@ -92,6 +100,20 @@ _SIGS = {
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
     "blasfeo_hip_plan_set_config": (_i, [_p, _p, _i]),
     "blasfeo_hip_plan_destroy": (None, [_p]),
+    "blasfeo_memsize_smat": (_i, [_i, _i]),
+    "blasfeo_create_smat": (None, [_i, _i, _S, _p]),
+    "blasfeo_allocate_smat": (None, [_i, _i, _S]),
+    "blasfeo_free_smat": (None, [_S]),
+    "blasfeo_pack_smat": (None, [_i, _i, _p, _i, _S, _i, _i]),
+    "blasfeo_unpack_smat": (None, [_i, _i, _S, _i, _i, _p, _i]),
+    "blasfeo_hip_pack_smat_batched": (_i, [_i, _i, _i, _p, _i, _ll, _S, _i, _i, _p]),
+    "blasfeo_hip_unpack_smat_batched": (_i, [_i, _i, _i, _S, _i, _i, _p, _i, _ll, _p]),
+    "blasfeo_sgemm_nt": (None, [_i, _i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i]),
+    "blasfeo_ssyrk_ln": (None, [_i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i]),
+    "blasfeo_spotrf_l": (None, [_i, _S, _i, _i, _S, _i, _i]),
+    "blasfeo_hip_sgemm_nt_batched": (_i, [_i, _i, _i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i, _p]),
+    "blasfeo_hip_ssyrk_ln_batched": (_i, [_i, _i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i, _p]),
+    "blasfeo_hip_spotrf_l_batched": (_i, [_i, _i, _S, _i, _i, _S, _i, _i, _p, _p]),
     "blasfeo_hip_plan_enable_mixed": (_i, [_p, ctypes.POINTER(_ll)]),
     "blasfeo_hip_dposv_mixed_vbatched": (_i, [_p, _i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_mixed_factor": (_i, [_p, _i, _p, _i, _p]),
@@ -270,6 +292,139 @@ def unpack_batch(sA, m=None, n=None):
     check(lib().blasfeo_hip_unpack_dmat_batched(sA.batch, m, n, sA.ref, 0, 0, ctypes.c_void_p(out.data_ptr()),
                                                 max(m, 1), m * n, _stream()))
     return out.transpose(1, 2)
+
+
+# ------------------------------------------------------------------ single precision
+
+PS_S = 32
+
+
+class SMat:
+    """A device single-precision panel-major matrix (32-float panels) with its
+    struct blasfeo_smat."""
+
+    def __init__(self, m, n, device="cuda"):
+        torch = _torch()
+        self.s = blasfeo_smat()
+        ms = lib().blasfeo_memsize_smat(m, n)
+        if ms < 0:
+            raise ValueError("bad size")
+        self.buf = torch.empty(max(ms, 256) // 4, dtype=torch.float32, device=device)
+        lib().blasfeo_create_smat(m, n, ctypes.byref(self.s), ctypes.c_void_p(self.buf.data_ptr()))
+        self.m, self.n = m, n
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    def dA(self):
+        off = self.s.pm * PS_S * self.s.cn
+        return self.buf[off: off + max(self.m, self.n)]
+
+
+class SMatBatch:
+    """`batch` consecutive SMat chunks of memsize bytes; .s describes instance 0."""
+
+    def __init__(self, batch, m, n, device="cuda"):
+        torch = _torch()
+        self.batch, self.m, self.n = batch, m, n
+        self.stride = lib().blasfeo_memsize_smat(m, n) // 4
+        self.buf = torch.empty(max(batch * self.stride, 64), dtype=torch.float32, device=device)
+        self.s = blasfeo_smat()
+        lib().blasfeo_create_smat(m, n, ctypes.byref(self.s), ctypes.c_void_p(self.buf.data_ptr()))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    def instances(self):
+        return self.buf[: self.batch * self.stride].view(self.batch, self.stride)
+
+    def dA(self):
+        off = self.s.pm * PS_S * self.s.cn
+        return self.instances()[:, off: off + max(self.m, self.n)]
+
+
+def spack(A, out=None, bi=0, bj=0):
+    """(m, n) tensor -> SMat through blasfeo_pack_smat."""
+    torch = _torch()
+    m, n = A.shape
+    At = A.t().contiguous().to(torch.float32)
+    if out is None:
+        out = SMat(m, n, device=A.device)
+    _sync_stream()
+    lib().blasfeo_pack_smat(m, n, ctypes.c_void_p(At.data_ptr()), max(m, 1), out.ref, bi, bj)
+    check_last()
+    return out
+
+
+def sunpack(sA, m=None, n=None, ai=0, aj=0):
+    """(m, n) float32 tensor of the sub-matrix of SMat sA at (ai, aj)."""
+    torch = _torch()
+    m = sA.m - ai if m is None else m
+    n = sA.n - aj if n is None else n
+    out = torch.empty((n, m), dtype=torch.float32, device=sA.buf.device)
+    _sync_stream()
+    lib().blasfeo_unpack_smat(m, n, sA.ref, ai, aj, ctypes.c_void_p(out.data_ptr()), max(m, 1))
+    check_last()
+    return out.t()
+
+
+def spack_batch(A, out=None):
+    """(batch, m, n) tensor -> SMatBatch via the batched pack."""
+    torch = _torch()
+    batch, m, n = A.shape
+    At = A.transpose(1, 2).contiguous().to(torch.float32)
+    if out is None:
+        out = SMatBatch(batch, m, n, device=A.device)
+    check(lib().blasfeo_hip_pack_smat_batched(batch, m, n, ctypes.c_void_p(At.data_ptr()), max(m, 1),
+                                              m * n, out.ref, 0, 0, _stream()))
+    return out
+
+
+def sunpack_batch(sA, m=None, n=None):
+    torch = _torch()
+    m = sA.m if m is None else m
+    n = sA.n if n is None else n
+    out = torch.empty((sA.batch, n, m), dtype=torch.float32, device=sA.buf.device)
+    check(lib().blasfeo_hip_unpack_smat_batched(sA.batch, m, n, sA.ref, 0, 0, ctypes.c_void_p(out.data_ptr()),
+                                                max(m, 1), m * n, _stream()))
+    return out.transpose(1, 2)
+
+
+def blasfeo_sgemm_nt(m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_sgemm_nt(m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_ssyrk_ln(m, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_ssyrk_ln(m, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_spotrf_l(m, sC, ci, cj, sD, di, dj):
+    _sync_stream()
+    lib().blasfeo_spotrf_l(m, sC.ref, ci, cj, sD.ref, di, dj)
+    check_last()
+
+
+def blasfeo_hip_sgemm_nt_batched(batch, m, n, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
+                                 stream=None):
+    return check(lib().blasfeo_hip_sgemm_nt_batched(batch, m, n, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
+                                                    sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_ssyrk_ln_batched(batch, m, k, alpha, sA, ai, aj, sB, bi, bj, beta, sC, ci, cj, sD, di, dj,
+                                 stream=None):
+    return check(lib().blasfeo_hip_ssyrk_ln_batched(batch, m, k, alpha, sA.ref, ai, aj, sB.ref, bi, bj, beta,
+                                                    sC.ref, ci, cj, sD.ref, di, dj, _stream(stream)))
+
+
+def blasfeo_hip_spotrf_l_batched(batch, m, sC, ci, cj, sD, di, dj, info, stream=None):
+    return check(lib().blasfeo_hip_spotrf_l_batched(batch, m, sC.ref, ci, cj, sD.ref, di, dj, _ptr(info),
+                                                    _stream(stream)))
 
 
 # ------------------------------------------------------------------ routines (C ABI names)
