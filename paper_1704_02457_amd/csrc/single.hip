@@ -62,6 +62,15 @@ __device__ __forceinline__ float sload_frag(const SView &v, int i0, int k0) {
   return ok ? x : 0.0f;
 }
 
+// The same fragment without the final select: elements outside S come from
+// S's origin (any finite value), for callers that mask later.
+__device__ __forceinline__ float sload_frag_raw(const SView &v, int i0, int k0) {
+  const int l = lane_id();
+  const int i = i0 + (l & 15), k = k0 + (l >> 4);
+  const bool ok = i < v.rows && k < v.cols;
+  return v.p[ok ? pm_off_s(v.ai + i, v.aj + k, v.cn) : pm_off_s(v.ai, v.aj, v.cn)];
+}
+
 // T32 tile of block S(i0.., j0..): register r of lane (c, g) = S[i0 + 4g + r][j0 + c]
 // (trans: S[i0 + c][j0 + 4g + r]); zero outside S and, with lower, where
 // the block's row index is below its column index
@@ -160,8 +169,12 @@ static int launch_spack(int batch, int m, int n, const float *A, int lda, long l
 }
 
 // ---------------------------------------------------------------- gemm/syrk
-// One wave per 16x16 block of D: D(i,j) = beta C(i,j) + alpha sum_k A_i B_j^T,
-// one FP32 MFMA per 4-wide k-step, both factors read along panels.
+// One wave per 64x64 block of D (4x4 tiles of 16x16): per 4-wide k-step it
+// loads four fragments of A and four of B and issues the 16 FP32 MFMAs of
+// their outer product, D = beta C + alpha sum_k A B^T.  The accumulators hold
+// D^T (B fragment first) so that the lanes of a store run down a panel
+// column: 64-byte contiguous segments instead of scattered words.  syrk_ln takes the
+// blocks on and below the diagonal and stores the lower triangle only.
 template <bool SYRK>
 __global__ __launch_bounds__(256) void k_sgemm_nt(int m, int n, int k, float alpha, SView A,
                                                   SView B, float beta, SView C, SView D,
@@ -171,28 +184,73 @@ __global__ __launch_bounds__(256) void k_sgemm_nt(int m, int n, int k, float alp
   B = sat_batch(B, sB);
   C = sat_batch(C, sC);
   D = sat_batch(D, sD);
-  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
-  const int tile = blockIdx.x * 4 + wave_id();
-  int ti, tj;
+  const int bm = (m + 63) >> 6, bn = (n + 63) >> 6;
+  const int blk = blockIdx.x * 4 + wave_id();
+  int bi, bj;
   if (SYRK) {
-    if (tile >= tm * (tm + 1) / 2) return;
-    ti = 0;
-    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-    tj = tile - ti * (ti + 1) / 2;
+    if (blk >= bm * (bm + 1) / 2) return;
+    bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+    bj = blk - bi * (bi + 1) / 2;
   } else {
-    if (tile >= tm * tn) return;
-    ti = tile / tn;
-    tj = tile - ti * tn;
+    if (blk >= bm * bn) return;
+    bi = blk / bn;
+    bj = blk - bi * bn;
   }
-  f4s acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < k; k0 += 4)
-    acc = smfma(sload_frag(A, 16 * ti, k0), sload_frag(B, 16 * tj, k0), acc);
-  const bool diag = SYRK && ti == tj;
-  const f4s ct = sload_tile(C, 16 * ti, 16 * tj, false, diag);
-  f4s out;
+  const int i0 = 64 * bi, j0 = 64 * bj;
+  f4s acc[4][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] = beta * ct[r] + alpha * acc[r];
-  sstore_tile(D, 16 * ti, 16 * tj, out, false, diag);
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = (f4s){0.f, 0.f, 0.f, 0.f};
+  // Fragments of step k0 + 4 are loaded before the MFMAs of step k0, and
+  // scheduling barriers keep the compiler from moving them (or the waits for
+  // them) back.  Rows of A or B beyond m or n only reach rows or columns of
+  // the accumulators that are never stored, so only the k index is masked,
+  // on the B fragment, after the MFMAs.
+  const int g = lane_id() >> 4;
+  float fa[4] = {0.f, 0.f, 0.f, 0.f}, fb[4] = {0.f, 0.f, 0.f, 0.f};
+  if (k > 0) {  // k == 0: A and B are empty views without storage
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fa[t] = sload_frag_raw(A, i0 + 16 * t, 0);
+      const float x = sload_frag_raw(B, j0 + 16 * t, 0);
+      fb[t] = g < k ? x : 0.f;
+    }
+  }
+  for (int k0 = 0; k0 < k; k0 += 4) {
+    float na[4], nb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      na[t] = sload_frag_raw(A, i0 + 16 * t, k0 + 4);
+      nb[t] = sload_frag_raw(B, j0 + 16 * t, k0 + 4);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = smfma(fb[tj], fa[ti], acc[ti][tj]);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool kin = k0 + 4 + g < k;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fa[t] = na[t];
+      fb[t] = kin ? nb[t] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      const int r0 = i0 + 16 * ti, c0 = j0 + 16 * tj;
+      if (r0 >= m || c0 >= n || (SYRK && c0 > r0)) continue;
+      const bool diag = SYRK && r0 == c0;
+      const f4s ct = sload_tile(C, r0, c0, true, diag);
+      f4s out;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[r] = beta * ct[r] + alpha * acc[ti][tj][r];
+      sstore_tile(D, r0, c0, out, true, diag);
+    }
 }
 
 // ---------------------------------------------------------------- potrf_l
@@ -262,14 +320,75 @@ __global__ __launch_bounds__(256) void k_spotrf_l(int m, SView C, SView D, float
   if (info && threadIdx.x == 0) info[b] = s.info;
 }
 
+// m <= 16*NB <= 64: one wave per instance with the whole lower triangle in
+// registers as T32 tiles T(j,i) = C(i,j)^T, right-looking: for each block
+// column the FP64 diagonal routine, T(j,i) = V^T T(j,i) = L(i,j)^T for the
+// blocks below, and the trailing downdates T(q,i) -= T(j,q)^T T(j,i) on the
+// FP32 MFMA.  Every block is read and written once, with no barrier.
+template <int NB>
+__global__ __launch_bounds__(64) void k_spotrf_reg(int m, SView C, SView D, float *dA, int *info,
+                                                   long long sC, long long sD, long long sdA) {
+  struct Lds {
+    DiagLds d;
+    double tr[16 * 17];
+  };
+  __shared__ Lds s;
+  C = sat_batch(C, sC);
+  D = sat_batch(D, sD);
+  const long long b = blockIdx.y;
+  float *dAb = dA ? dA + b * sdA : nullptr;
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  constexpr int NT = NB * (NB + 1) / 2;
+  f4s T[NT];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) T[tix_up(j, i)] = sload_tile(C, 16 * i, 16 * j, true, i == j);
+  int inf0 = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int nv = min(16, m - 16 * j);
+    d4 Dj = st32_to_t64(T[tix_up(j, j)], s.tr);
+    pad_identity(Dj, nv);
+    d4 V;
+    const int inf = potrf_inv_tile_upper(Dj, V, s.d);
+    if (inf && inf0 == 0) inf0 = 16 * j + inf;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * j + c, col = 16 * j + g + 4 * r;
+      if (row < m && c >= g + 4 * r) D.p[pm_off_s(D.ai + row, D.aj + col, D.cn)] = (float)Dj[r];
+    }
+    if (dAb && l < nv) dAb[16 * j + l] = (float)s.d.inv[l];
+    const f4s V32 = st64_to_t32(V, s.tr);
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      T[tix_up(j, i)] = smfma_tn(V32, T[tix_up(j, i)], (f4s){0.f, 0.f, 0.f, 0.f});
+      sstore_tile(D, 16 * i, 16 * j, T[tix_up(j, i)], true, false);
+    }
+#pragma unroll
+    for (int q = j + 1; q < NB; ++q) {
+      const f4s nq = -T[tix_up(j, q)];
+#pragma unroll
+      for (int i = q; i < NB; ++i) T[tix_up(q, i)] = smfma_tn(nq, T[tix_up(j, i)], T[tix_up(q, i)]);
+    }
+  }
+  if (info && l == 0) info[b] = inf0;
+}
+
+__global__ void k_sfill_int(int *p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
 static int launch_sgemm(bool syrk, int batch, int m, int n, int k, float alpha,
                         const blasfeo_smat *sA, int ai, int aj, const blasfeo_smat *sB, int bi,
                         int bj, float beta, const blasfeo_smat *sC, int ci, int cj,
                         const blasfeo_smat *sD, int di, int dj, hipStream_t st) {
   if (batch == 0 || m == 0 || n == 0) return 0;
-  const int tm = (m + 15) / 16, tn = (n + 15) / 16;
-  const int tiles = syrk ? tm * (tm + 1) / 2 : tm * tn;
-  const dim3 grid((tiles + 3) / 4, batch);
+  const int bm = (m + 63) / 64, bn = (n + 63) / 64;
+  const int blocks = syrk ? bm * (bm + 1) / 2 : bm * bn;
+  const dim3 grid((blocks + 3) / 4, batch);
   const SView A = k > 0 ? make_sview(sA, ai, aj, m, k) : SView{};
   const SView B = k > 0 ? make_sview(sB, bi, bj, n, k) : SView{};
   const SView C = make_sview(sC, ci, cj, m, n), D = make_sview(sD, di, dj, m, n);
@@ -287,15 +406,20 @@ static int launch_spotrf(int batch, int m, const blasfeo_smat *sC, int ci, int c
                          const blasfeo_smat *sD, int di, int dj, int *info, hipStream_t st) {
   if (batch == 0) return 0;
   if (m == 0) {
-    if (info) {
-      const hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * (size_t)batch, st);
-      if (e != hipSuccess) return (int)e;
-    }
-    return 0;
+    if (info) hipLaunchKernelGGL(k_sfill_int, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch, 0);
+    return launch_status();
   }
   const SView C = make_sview(sC, ci, cj, m, m), D = make_sview(sD, di, dj, m, m);
-  hipLaunchKernelGGL(k_spotrf_l, dim3(1, batch), dim3(256), 0, st, m, C, D, sD->dA, info,
-                     sbatch_stride(sC), sbatch_stride(sD), sbatch_stride(sD));
+  const long long ssC = sbatch_stride(sC), ssD = sbatch_stride(sD);
+  const dim3 g(1, batch);
+  switch ((m + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_spotrf_reg<1>, g, dim3(64), 0, st, m, C, D, sD->dA, info, ssC, ssD, ssD); break;
+    case 2: hipLaunchKernelGGL(k_spotrf_reg<2>, g, dim3(64), 0, st, m, C, D, sD->dA, info, ssC, ssD, ssD); break;
+    case 3: hipLaunchKernelGGL(k_spotrf_reg<3>, g, dim3(64), 0, st, m, C, D, sD->dA, info, ssC, ssD, ssD); break;
+    case 4: hipLaunchKernelGGL(k_spotrf_reg<4>, g, dim3(64), 0, st, m, C, D, sD->dA, info, ssC, ssD, ssD); break;
+    default:
+      hipLaunchKernelGGL(k_spotrf_l, g, dim3(256), 0, st, m, C, D, sD->dA, info, ssC, ssD, ssD);
+  }
   return launch_status();
 }
 
