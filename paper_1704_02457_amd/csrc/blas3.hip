@@ -332,70 +332,96 @@ __global__ void k_fill_int(int *p, int count, int v) {
 
 // ---------------------------------------------------------------- getrf
 // LU with (PIVOT) or without partial pivoting of an m-by-n matrix, m, n <=
-// 64 (§5.2.2, getrf): one wave per instance, the matrix in LDS with lane i
-// owning row i, the right-looking unblocked sweep of the oracle (pivot =
-// first row of largest magnitude by a wave argmax, rows swapped in LDS,
-// multipliers by the reciprocal, rank-1 trailing update).  Contraction into
-// fused multiply-adds is switched off so that every operation rounds as the
-// oracle's does and the pivot choices agree.
+// 64 (§5.2.2, getrf): one wave per instance with lane i holding row i of
+// the matrix in 64 registers, the right-looking unblocked sweep of the
+// oracle.  Rows are never moved: each lane keeps the current position of its
+// row, an interchange swaps two positions, and the rows are stored to their
+// final positions at the end.  Step k: the pivot is the row of largest
+// magnitude in column k among positions >= k, ties to the smallest position
+// (a wave argmax), the multipliers are formed with the pivot's reciprocal and
+// the pivot row's entries reach the other lanes by readlane for the rank-1
+// update (NaN entries in column k are ranked as the oracle's scan ranks
+// them).  Contraction into fused multiply-adds is off, so every operation
+// rounds as the oracle's does and the pivot choices agree.  Column k lives
+// in register 16*qb + kk: the 16 steps of a block of columns select it from
+// the block's 16 registers, and the update runs over the columns from the
+// block on, so registers are indexed at compile time.
 template <bool PIVOT>
 __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, double *dA,
                                               int *ipiv, int *info, long long sC,
                                               long long sD, long long sdA, long long sip) {
 #pragma clang fp contract(off)
-  __shared__ double a[64][65];
   C = at_batch(C, sC);
   D = at_batch(D, sD);
   const long long b = blockIdx.y;
   double *dAb = dA ? dA + b * sdA : nullptr;
   int *ipb = ipiv ? ipiv + b * sip : nullptr;
   const int l = lane_id();
+  const bool live = l < m;
   const int lr = min(l, m - 1);
-  for (int j = 0; j < n; ++j) {
-    const double x = C.p[pm_off(C.ai + lr, C.aj + j, C.cn)];  // clamped row: no branch
-    a[l][j] = l < m ? x : 0.0;
+  double r[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const double x = C.p[pm_off(C.ai + lr, C.aj + min(c, n - 1), C.cn)];  // clamped: no branch
+    r[c] = (live && c < n) ? x : 0.0;
   }
-  wave_sync();
+  int pos = l;
   int inf = 0;
   const int mn = min(m, n);
-  for (int k = 0; k < mn; ++k) {
-    int p = k;
-    if (PIVOT) {
-      double v = (l >= k && l < m) ? fabs(a[l][k]) : -1.0;
-      int idx = l;
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        const double v2 = __shfl_xor(v, o);
-        const int i2 = __shfl_xor(idx, o);
-        if (v2 > v || (v2 == v && i2 < idx)) {
-          v = v2;
-          idx = i2;
+  for (int qb = 0; qb < 4; ++qb) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * qb + kk;
+      if (k >= mn) break;
+      double v = r[16 * qb];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) v = kk == e ? r[16 * qb + e] : v;
+      int pl = k, ppos = k;
+      if (PIVOT) {
+        // the oracle's scan keeps position k unless a later row is strictly
+        // larger, so a NaN there wins and a NaN elsewhere never does
+        const double av = __builtin_isnan(v) ? (pos == k ? __builtin_inf() : -0.5) : fabs(v);
+        double key = (live && pos >= k) ? av : -1.0;
+        int kp = pos;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const double k2 = __shfl_xor(key, o);
+          const int p2 = __shfl_xor(kp, o);
+          if (k2 > key || (k2 == key && p2 < kp)) {
+            key = k2;
+            kp = p2;
+          }
+        }
+        ppos = __builtin_amdgcn_readfirstlane(kp);
+        pl = __ffsll((unsigned long long)__ballot(live && pos == ppos)) - 1;
+        const int kl = __ffsll((unsigned long long)__ballot(live && pos == k)) - 1;
+        if (l == kl) pos = ppos;
+        if (l == pl) pos = k;
+      }
+      if (ipb && l == 0) ipb[k] = ppos;
+      const double piv = readlane_d(v, pl);
+      if (piv == 0.0 && inf == 0) inf = k + 1;
+      const double inv = 1.0 / piv;
+      if (dAb && l == 0) dAb[k] = inv;
+      const bool below = live && pos > k;
+      const double mult = v * inv;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) r[16 * qb + e] = (below && kk == e) ? mult : r[16 * qb + e];
+#pragma unroll
+      for (int c = 16 * qb; c < 64; ++c) {
+        if (c < n) {
+          const double pc = readlane_d(r[c], pl);
+          const double upd = r[c] - mult * pc;
+          r[c] = (below && c > k) ? upd : r[c];
         }
       }
-      p = __builtin_amdgcn_readfirstlane(idx);
-      if (p != k) {
-        if (l < n) {
-          const double t = a[k][l];
-          a[k][l] = a[p][l];
-          a[p][l] = t;
-        }
-        wave_sync();
-      }
     }
-    if (ipb && l == 0) ipb[k] = p;
-    const double piv = a[k][k];
-    if (piv == 0.0 && inf == 0) inf = k + 1;
-    const double inv = 1.0 / piv;
-    if (dAb && l == 0) dAb[k] = inv;
-    if (l > k && l < m) {
-      const double mult = a[l][k] * inv;
-      a[l][k] = mult;
-      for (int j = k + 1; j < n; ++j) a[l][j] -= mult * a[k][j];
-    }
-    wave_sync();
   }
-  if (l < m)
-    for (int j = 0; j < n; ++j) D.p[pm_off(D.ai + l, D.aj + j, D.cn)] = a[l][j];
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c)
+      if (c < n) D.p[pm_off(D.ai + pos, D.aj + c, D.cn)] = r[c];
+  }
   if (info && l == 0) info[b] = inf;
 }
 
