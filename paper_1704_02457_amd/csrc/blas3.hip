@@ -427,55 +427,83 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
 
 // ---------------------------------------------------------------- gelqf
 // LQ factorization by Householder reflectors of an m-by-n matrix, m, n <= 64
-// (§5.2.2, gelqf; unblocked): one wave per instance, the matrix in LDS with
-// lane i owning row i.  Row k's reflector: the squared norm of its part right
-// of the diagonal by a wave sum, the scalars of the oracle, the vector
-// scaled in place; then every row below forms its product with the
-// reflector and subtracts.  tau goes to dA.  Contraction is off, as in the
-// oracle; only the order of the norm's sum differs.
+// (§5.2.2, gelqf; unblocked): one wave per instance with lane i holding row
+// i in 64 registers.  Step k: every lane forms the squared norm of its row
+// right of column k in ascending column order (the oracle's order; lane k's
+// is the one used), the oracle's scalars follow, lane k scales its row into
+// the reflector, whose entries reach the other lanes by readlane, and every
+// row below forms its product with the reflector and subtracts.  tau goes
+// to dA.  Contraction is off, as in the oracle, so each operation rounds as
+// the oracle's does.  Column k is register 16*qb + kk, selected as in getrf.
 __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, double *tau,
                                               long long sC, long long sD, long long stau) {
 #pragma clang fp contract(off)
-  __shared__ double a[64][65];
   C = at_batch(C, sC);
   D = at_batch(D, sD);
   const long long b = blockIdx.y;
   double *taub = tau + b * stau;
   const int l = lane_id();
+  const bool live = l < m;
   const int lr = min(l, m - 1);
-  for (int j = 0; j < n; ++j) {
-    const double x = C.p[pm_off(C.ai + lr, C.aj + j, C.cn)];
-    a[l][j] = l < m ? x : 0.0;
-  }
-  wave_sync();
-  const int mn = min(m, n);
-  for (int k = 0; k < mn; ++k) {
-    const double alpha = a[k][k];
-    double sq = (l > k && l < n) ? a[k][l] * a[k][l] : 0.0;
+  double r[64];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o);
-    double t = 0.0;
-    if (sq != 0.0) {
-      const double beta = -copysign(sqrt(alpha * alpha + sq), alpha);
-      t = (beta - alpha) / beta;
-      const double sc = 1.0 / (alpha - beta);
-      wave_sync();
-      if (l > k && l < n) a[k][l] *= sc;
-      if (l == 0) a[k][k] = beta;
-    }
-    if (l == 0) taub[k] = t;
-    wave_sync();
-    if (t != 0.0 && l > k && l < m) {
-      double w = a[l][k];
-      for (int j = k + 1; j < n; ++j) w += a[l][j] * a[k][j];
-      w *= t;
-      a[l][k] -= w;
-      for (int j = k + 1; j < n; ++j) a[l][j] -= w * a[k][j];
-    }
-    wave_sync();
+  for (int c = 0; c < 64; ++c) {
+    const double x = C.p[pm_off(C.ai + lr, C.aj + min(c, n - 1), C.cn)];  // clamped: no branch
+    r[c] = (live && c < n) ? x : 0.0;
   }
-  if (l < m)
-    for (int j = 0; j < n; ++j) D.p[pm_off(D.ai + l, D.aj + j, D.cn)] = a[l][j];
+  const int mn = min(m, n);
+#pragma unroll
+  for (int qb = 0; qb < 4; ++qb) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * qb + kk;
+      if (k >= mn) break;
+      double rk = r[16 * qb];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) rk = kk == e ? r[16 * qb + e] : rk;
+      double ss = 0.0;
+#pragma unroll
+      for (int c = 16 * qb; c < 64; ++c)
+        if (c < n) ss = c > k ? ss + r[c] * r[c] : ss;
+      const double alpha = readlane_d(rk, k);
+      const double ssk = readlane_d(ss, k);
+      double t = 0.0;
+      if (sqrt(ssk) != 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + ssk), alpha);
+        t = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+        const bool me = l == k;
+#pragma unroll
+        for (int c = 16 * qb; c < 64; ++c)
+          if (c < n) r[c] = (me && c > k) ? r[c] * sc : r[c];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) r[16 * qb + e] = (me && kk == e) ? beta : r[16 * qb + e];
+      }
+      if (l == 0) taub[k] = t;
+      if (t == 0.0) continue;
+      // rows below: w = (r[k] + sum_{c>k} r[c] v[c]) t, then r -= w v (v[k] = 1)
+      // (the reflector's entries are read twice by readlane rather than
+      // held: 48 of them would not fit next to the row)
+      const bool below = live && l > k;
+      double w = rk;
+#pragma unroll
+      for (int c = 16 * qb; c < 64; ++c)
+        if (c < n) w = c > k ? w + r[c] * readlane_d(r[c], k) : w;
+      w *= t;
+#pragma unroll
+      for (int c = 16 * qb; c < 64; ++c) {
+        if (c < n) {
+          const bool diag = c - 16 * qb == kk;
+          const double upd = diag ? r[c] - w : r[c] - w * readlane_d(r[c], k);
+          r[c] = (below && c >= k) ? upd : r[c];
+        }
+      }
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c)
+      if (c < n) D.p[pm_off(D.ai + l, D.aj + c, D.cn)] = r[c];
+  }
 }
 
 int launch_gelqf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj,
