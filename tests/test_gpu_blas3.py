@@ -338,6 +338,10 @@ def test_dgetrf(m, n, pivot, off):
         assert np.array_equal(ipiv.cpu().numpy(), ipr)
     assert_parity(Dfull[di:, dj:], Dr, max(m, n), "getrf")
     assert_parity(sD.dA()[:mn].cpu().numpy(), dAr, max(m, n), "dA")
+    # the kernel performs the oracle's operations in the oracle's order, in
+    # IEEE binary64 without contraction on both sides: identical bits
+    assert np.array_equal(Dfull[di:, dj:], Dr)
+    assert np.array_equal(sD.dA()[:mn].cpu().numpy(), dAr)
     mask = np.ones_like(Dfull, dtype=bool)
     mask[di:, dj:] = False
     assert np.all(Dfull[mask] == SENT)
@@ -399,6 +403,9 @@ def test_dgelqf(m, n, off):
     Dr, taur = oracle.dgelqf(A)
     assert_parity(D, Dr, max(m, n), "gelqf")
     assert_parity(tau, taur, max(m, n), "tau")
+    # same operations in the same order (the norm summed by ascending
+    # column), correctly rounded sqrt and division, no contraction: same bits
+    assert np.array_equal(D, Dr) and np.array_equal(tau, taur)
     Q = oracle.lq_q(D, tau)
     k = min(m, n)
     assert np.abs(np.tril(D)[:, :k] @ Q[:k] - A).max() <= 1e-13 * max(m, n)
