@@ -228,8 +228,73 @@ __device__ __forceinline__ double vel(const View &v, int i, int j) {
   return v.p[pm_off(v.ai + i, v.aj + j, v.cn)];
 }
 
+// Copy of the rows x cols matrix v into LDS (row i at dst + i * ld), the lanes
+// running down the panel columns.
+__device__ __forceinline__ void stage_lds(const View &v, int rows, int cols, double *dst, int ld) {
+  for (int t = lane_id(); t < rows * cols; t += 64) {
+    const int i = t % rows, j = t / rows;
+    dst[i * ld + j] = vel(v, i, j);
+  }
+}
+
+// The stage factor F_n (nm x nm, nm <= 48) in flight in registers: element
+// t = lane + 64 s of the column-major enumeration in pf[s].
+constexpr int kRicPf = 36;  // 48 * 48 / 64
+
+struct RicPf {
+  double v[kRicPf];
+};
+
+__device__ __forceinline__ void ric_pf_load(RicPf &pf, const double *F, int cn, int nm) {
+  // buffer loads: element offsets past the descriptor's range read 0
+  const int pm = (nm + 15) >> 4;
+  const brsrc rs = make_rsrc(F, 8LL * pm * 16 * cn);
+  const int l = lane_id();
+  int i = l % nm, j = l / nm;
+  const int di = 64 % nm, dj = 64 / nm;
+#pragma unroll
+  for (int s = 0; s < kRicPf; ++s) {
+    const int off = j < nm ? 8 * ((i & ~15) * cn + j * 16 + (i & 15)) : 0x7ffffff0;
+    pf.v[s] = bload(rs, off, 0);
+    i += di;
+    j += dj;
+    if (i >= nm) {
+      i -= nm;
+      ++j;
+    }
+  }
+}
+
+__device__ __forceinline__ void ric_pf_store(const RicPf &pf, double *Fs, int nm) {
+  const int l = lane_id();
+  int i = l % nm, j = l / nm;
+  const int di = 64 % nm, dj = 64 / nm;
+#pragma unroll
+  for (int s = 0; s < kRicPf; ++s) {
+    if (j < nm) Fs[i * (nm + 1) + j] = pf.v[s];
+    i += di;
+    j += dj;
+    if (i >= nm) {
+      i -= nm;
+      ++j;
+    }
+  }
+}
+
+size_t ric_trs_lds_bytes(int nx, int nu) {
+  const int nm = nx + nu;
+  return sizeof(double) * ((size_t)nx * (nx + 1) + (size_t)nx * (nu + 1) + (size_t)nm * (nm + 1) + 4 * 64);
+}
+
+// Solve of the Riccati problem on the stored stage factors, one wave per
+// problem, lane = vector row.  A and B are copied to LDS once and each stage
+// factor once per pass (padded rows, so that row- and column-wise reads are
+// both free of bank conflicts); every matrix-vector product reads LDS.  The
+// global loads that a stage waits for go out early: the factor's while the
+// previous factor is still in use, the stage vectors (b, r, q, and l in the
+// forward pass) one stage ahead.
 __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
-  __shared__ double sv[4][64];
+  extern __shared__ double lds[];
   const long long pb = blockIdx.x;
   if (pb >= a.batch) return;
   const int l = lane_id();
@@ -238,18 +303,33 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
   A.p += pb * a.sA;
   B.p += pb * a.sB;
   P.p += pb * a.sP;
-  auto Fv = [&](int n) {
-    return View{const_cast<double *>(a.F) + (pb * N + n) * a.sF, a.cnF, 0, 0, nm, nm};
-  };
+  const int la = nx + 1, lb = nu + 1, lf = nm + 1;
+  double *As = lds, *Bs = As + nx * la, *Fs = Bs + nx * lb;
+  double *vt = Fs + nm * lf, *vm = vt + 64, *vp = vm + 64, *vx = vp + 64;
+  auto Fp = [&](int n) { return a.F + (pb * N + n) * a.sF; };
   const double *bv = a.b + pb * N * nx, *rv = a.r + pb * N * nu;
   const double *qv = a.q + pb * (N + 1) * nx, *x0 = a.x0 + pb * nx;
   double *u = a.u + pb * N * nu, *x = a.x + pb * (N + 1) * nx;
-  double *vt = sv[0], *vm = sv[1], *vp = sv[2], *vx = sv[3];
+  auto F = [&](int i, int j) { return Fs[i * lf + j]; };
 
+  RicPf pf;
+  stage_lds(A, nx, nx, As, la);
+  stage_lds(B, nx, nu, Bs, lb);
   // ------------------------------------------------ backward: p_n and l_n
   if (l < nx) vp[l] = qv[(long long)N * nx + l];
+  // the stage vectors are loaded one stage ahead
+  const int lx = min(l, nx - 1), lu = min(l, nu - 1), lq = min(max(l - nu, 0), nx - 1);
+  double bnx = bv[(long long)(N - 1) * nx + lx], rnx = rv[(long long)(N - 1) * nu + lu];
+  double qnx = qv[(long long)(N - 1) * nx + lq];
   for (int n = N - 1; n >= 0; --n) {
-    if (l < nx) vt[l] = bv[(long long)n * nx + l];
+    const double bcur = bnx, rcur = rnx, qcur = qnx;
+    if (n > 0) {
+      bnx = bv[(long long)(n - 1) * nx + lx];
+      rnx = rv[(long long)(n - 1) * nu + lu];
+      qnx = qv[(long long)(n - 1) * nx + lq];
+    }
+    ric_pf_load(pf, Fp(n), a.cnF, nm);  // F_n's loads go out while F_{n+1} is used
+    if (l < nx) vt[l] = bcur;
     wave_sync();
     double w = 0.0;
     if (n == N - 1) {
@@ -258,17 +338,17 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
         #pragma unroll 8
         for (int k = 0; k < nx; ++k) w += vel(P, max(l, k), min(l, k)) * vt[k];
     } else {
-      const View Fn1 = Fv(n + 1);
-      double sj = 0.0;  // s = Lc' b, Lc = trailing block of F_{n+1}
+      // Fs holds F_{n+1}: s = Lc' b, Lc = its trailing block, then w = Lc s
+      double sj = 0.0;
       if (l < nx)
         #pragma unroll 8
-        for (int i = l; i < nx; ++i) sj += vel(Fn1, nu + i, nu + l) * vt[i];
+        for (int i = l; i < nx; ++i) sj += F(nu + i, nu + l) * vt[i];
       wave_sync();
       if (l < nx) vt[l] = sj;
       wave_sync();
       if (l < nx)
         #pragma unroll 8
-        for (int k = 0; k <= l; ++k) w += vel(Fn1, nu + l, nu + k) * vt[k];
+        for (int k = 0; k <= l; ++k) w += F(nu + l, nu + k) * vt[k];
     }
     if (l < nx) w += vp[l];
     wave_sync();
@@ -277,23 +357,25 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
     // m = [r_n + B'w; q_n + A'w], lane = row of m
     double mv = 0.0;
     if (l < nu) {
-      mv = rv[(long long)n * nu + l];
+      mv = rcur;
       #pragma unroll 8
-      for (int i = 0; i < nx; ++i) mv += vel(B, i, l) * vt[i];
+      for (int i = 0; i < nx; ++i) mv += Bs[i * lb + l] * vt[i];
     } else if (l < nm) {
-      mv = qv[(long long)n * nx + l - nu];
+      mv = qcur;
       #pragma unroll 8
-      for (int i = 0; i < nx; ++i) mv += vel(A, i, l - nu) * vt[i];
+      for (int i = 0; i < nx; ++i) mv += As[i * la + l - nu] * vt[i];
     }
     if (l < nm) vm[l] = mv;
     wave_sync();
+    // F_n replaces F_{n+1}; the loads of F_{n-1} go out
+    ric_pf_store(pf, Fs, nm);
+    wave_sync();
     // l_n = Lambda_n^{-1} m_u, column by column
-    const View Fn = Fv(n);
     for (int k = 0; k < nu; ++k) {
-      const double lk = vm[k] / vel(Fn, k, k);
+      const double lk = vm[k] / F(k, k);
       wave_sync();
       if (l == k) vm[l] = lk;
-      if (l > k && l < nu) vm[l] -= vel(Fn, l, k) * lk;
+      if (l > k && l < nu) vm[l] -= F(l, k) * lk;
       wave_sync();
     }
     if (l < nu) u[(long long)n * nu + l] = vm[l];  // l_n, overwritten by u_n below
@@ -301,7 +383,7 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
     if (l >= nu && l < nm) {
       pn = vm[l];
       #pragma unroll 8
-      for (int k = 0; k < nu; ++k) pn -= vel(Fn, l, k) * vm[k];
+      for (int k = 0; k < nu; ++k) pn -= F(l, k) * vm[k];
     }
     wave_sync();
     if (l >= nu && l < nm) vp[l - nu] = pn;
@@ -309,26 +391,33 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
   }
 
   // ------------------------------------------------ forward: u_n and x_n
+  // (Fs holds F_0)
   if (l < nx) {
     vx[l] = x0[l];
     x[l] = x0[l];
   }
+  double unx = u[lu], bfx = bv[lx];
   for (int n = 0; n < N; ++n) {
-    const View Fn = Fv(n);
+    const double ucur = unx, bfc = bfx;
+    if (n + 1 < N) ric_pf_load(pf, Fp(n + 1), a.cnF, nm);  // used from the next stage on
+    if (n + 1 < N) {
+      unx = u[(long long)(n + 1) * nu + lu];
+      bfx = bv[(long long)(n + 1) * nx + lx];
+    }
     wave_sync();
     double v = 0.0;  // L_n' x_n + l_n
     if (l < nu) {
       #pragma unroll 8
-      for (int i = 0; i < nx; ++i) v += vel(Fn, nu + i, l) * vx[i];
-      v += u[(long long)n * nu + l];
+      for (int i = 0; i < nx; ++i) v += F(nu + i, l) * vx[i];
+      v += ucur;
       vm[l] = v;
     }
     wave_sync();
     for (int k = nu - 1; k >= 0; --k) {  // Lambda_n^T y = v, row by row from the bottom
-      const double yk = vm[k] / vel(Fn, k, k);
+      const double yk = vm[k] / F(k, k);
       wave_sync();
       if (l == k) vm[l] = yk;
-      if (l < k) vm[l] -= vel(Fn, k, l) * yk;
+      if (l < k) vm[l] -= F(k, l) * yk;
       wave_sync();
     }
     if (l < nu) {
@@ -340,16 +429,17 @@ __global__ __launch_bounds__(64) void k_ric_trs(RicSolveArgs a) {
     double xn = 0.0;
     if (l < nx) {
       #pragma unroll 8
-      for (int k = 0; k < nx; ++k) xn += vel(A, l, k) * vx[k];
+      for (int k = 0; k < nx; ++k) xn += As[l * la + k] * vx[k];
       #pragma unroll 8
-      for (int k = 0; k < nu; ++k) xn += vel(B, l, k) * vm[k];
-      xn += bv[(long long)n * nx + l];
+      for (int k = 0; k < nu; ++k) xn += Bs[l * lb + k] * vm[k];
+      xn += bfc;
     }
     wave_sync();
     if (l < nx) {
       vx[l] = xn;
       x[(long long)(n + 1) * nx + l] = xn;
     }
+    if (n + 1 < N) ric_pf_store(pf, Fs, nm);
   }
 }
 
@@ -440,6 +530,6 @@ extern "C" int blasfeo_hip_dric_trs_batched(
   a.x0 = x0;
   a.u = u;
   a.x = x;
-  hipLaunchKernelGGL(k_ric_trs, dim3(batch), dim3(64), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(k_ric_trs, dim3(batch), dim3(64), ric_trs_lds_bytes(nx, nu), (hipStream_t)stream, a);
   return launch_status();
 }
