@@ -330,6 +330,25 @@ __global__ void k_fill_int(int *p, int count, int v) {
   if (i < count) p[i] = v;
 }
 
+// One step of a wave argmax by data-parallel primitives (DPP): every lane
+// that receives a (key, position) pair from the lane the control selects
+// keeps the better of the two (larger key, ties to the smaller position);
+// lanes without a source, or outside the rows of RM, receive an element
+// below every candidate.  The selection is a total order, so the result does
+// not depend on the reduction order.
+template <int CTRL, int RM>
+__device__ __forceinline__ void argmax_step(double &key, int &pos) {
+  const long long kb = __builtin_bit_cast(long long, key);
+  const long long ib = __builtin_bit_cast(long long, -3.0);
+  const int lo = __builtin_amdgcn_update_dpp((int)ib, (int)kb, CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ib >> 32), (int)(kb >> 32), CTRL, RM, 0xf, false);
+  const int p2 = __builtin_amdgcn_update_dpp(0x7fffffff, pos, CTRL, RM, 0xf, false);
+  const double k2 = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+  const bool take = k2 > key || (k2 == key && p2 < pos);
+  key = take ? k2 : key;
+  pos = take ? p2 : pos;
+}
+
 // ---------------------------------------------------------------- getrf
 // LU with (PIVOT) or without partial pivoting of an m-by-n matrix, m, n <=
 // 64 (§5.2.2, getrf): one wave per instance with lane i holding row i of
@@ -338,10 +357,10 @@ __global__ void k_fill_int(int *p, int count, int v) {
 // row, an interchange swaps two positions, and the rows are stored to their
 // final positions at the end.  Step k: the pivot is the row of largest
 // magnitude in column k among positions >= k, ties to the smallest position
-// (a wave argmax), the multipliers are formed with the pivot's reciprocal and
-// the pivot row's entries reach the other lanes by readlane for the rank-1
-// update (NaN entries in column k are ranked as the oracle's scan ranks
-// them).  Contraction into fused multiply-adds is off, so every operation
+// (a wave argmax on DPP, the result in lane 63), the multipliers are formed
+// with the pivot's reciprocal and the pivot row's entries reach the other
+// lanes by readlane for the rank-1 update (NaN entries in column k are
+// ranked as the oracle's scan ranks them).  Contraction into fused multiply-adds is off, so every operation
 // rounds as the oracle's does and the pivot choices agree.  Column k lives
 // in register 16*qb + kk: the 16 steps of a block of columns select it from
 // the block's 16 registers, and the update runs over the columns from the
@@ -383,16 +402,13 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
         const double av = __builtin_isnan(v) ? (pos == k ? __builtin_inf() : -0.5) : fabs(v);
         double key = (live && pos >= k) ? av : -1.0;
         int kp = pos;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const double k2 = __shfl_xor(key, o);
-          const int p2 = __shfl_xor(kp, o);
-          if (k2 > key || (k2 == key && p2 < kp)) {
-            key = k2;
-            kp = p2;
-          }
-        }
-        ppos = __builtin_amdgcn_readfirstlane(kp);
+        argmax_step<0x111, 0xf>(key, kp);  // row_shr:1
+        argmax_step<0x112, 0xf>(key, kp);  // row_shr:2
+        argmax_step<0x114, 0xf>(key, kp);  // row_shr:4
+        argmax_step<0x118, 0xf>(key, kp);  // row_shr:8: lane 15 of a row holds its best
+        argmax_step<0x142, 0xa>(key, kp);  // row_bcast:15 into rows 1 and 3
+        argmax_step<0x143, 0xc>(key, kp);  // row_bcast:31 into rows 2 and 3
+        ppos = __builtin_amdgcn_readlane(kp, 63);
         pl = __ffsll((unsigned long long)__ballot(live && pos == ppos)) - 1;
         const int kl = __ffsll((unsigned long long)__ballot(live && pos == k)) - 1;
         if (l == kl) pos = ppos;
