@@ -33,6 +33,24 @@ __device__ __forceinline__ double load_fragT(const View &v, int j0, int k0) {
   return ok ? x : 0.0;
 }
 
+constexpr int kGemmKU = 8;
+
+// Fragment loads without the final select (elements outside the view come
+// from its origin), for loops that issue a group of loads and mask after.
+__device__ __forceinline__ double load_frag_raw(const View &v, int i0, int k0) {
+  const int l = lane_id();
+  const int i = i0 + (l & 15), k = k0 + (l >> 4);
+  const bool ok = i < v.rows && k < v.cols;
+  return v.p[ok ? pm_off(v.ai + i, v.aj + k, v.cn) : pm_off(v.ai, v.aj, v.cn)];
+}
+
+__device__ __forceinline__ double load_fragT_raw(const View &v, int j0, int k0) {
+  const int l = lane_id();
+  const int j = j0 + (l & 15), k = k0 + (l >> 4);
+  const bool ok = k < v.rows && j < v.cols;
+  return v.p[ok ? pm_off(v.ai + k, v.aj + j, v.cn) : pm_off(v.ai, v.aj, v.cn)];
+}
+
 template <bool SYRK, bool NN = false>
 __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
     int m, int n, int k, double alpha, View A, View B, double beta, View C,
@@ -56,11 +74,26 @@ __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
     ti = tile / tn;
     tj = tile - ti * tn;
   }
+  // The k-loop in groups of kGemmKU steps whose fragment loads are all in
+  // flight together: the loads come first, a scheduling barrier keeps the
+  // compiler from interleaving them with their masks and the products, and
+  // the k index is masked afterwards on both operands (rows past m or n only
+  // reach accumulator rows or columns that are never stored).
+  const int g = lane_id() >> 4;
   d4 acc = zero4();
-  for (int k0 = 0; k0 < k; k0 += 4) {
-    const double fb = NN ? load_fragT(B, 16 * tj, k0) : load_frag(B, 16 * tj, k0);
-    const double fa = load_frag(A, 16 * ti, k0);
-    acc = mfma(fb, fa, acc);
+  for (int k0 = 0; k0 < k; k0 += 4 * kGemmKU) {
+    double fa[kGemmKU], fb[kGemmKU];
+#pragma unroll
+    for (int u = 0; u < kGemmKU; ++u) {
+      fb[u] = NN ? load_fragT_raw(B, 16 * tj, k0 + 4 * u) : load_frag_raw(B, 16 * tj, k0 + 4 * u);
+      fa[u] = load_frag_raw(A, 16 * ti, k0 + 4 * u);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kGemmKU; ++u) {
+      const bool kin = k0 + 4 * u + g < k;
+      acc = mfma(kin ? fb[u] : 0.0, kin ? fa[u] : 0.0, acc);
+    }
   }
   const d4 ct = load_tileT(C, 16 * ti, 16 * tj, SYRK);
   d4 out;
@@ -75,7 +108,8 @@ __global__ __launch_bounds__(64 * GW) void k_gemm_nt(
 // of D: D(i,j) = sum_{k >= j} B(i,k) A(k,j), i.e. a gemm_nt against A^T
 // whose k-loop starts at the block's first column (A(k,j) = 0 for k < j);
 // the A^T fragment of rows 16j..16j+15 is read column-wise from A and masked
-// to the lower triangle, so the diagonal block needs no special case.
+// to the lower triangle, so the diagonal block needs no special case.  (The
+// grouped loads of gemm_nt do not pay here: the k-loops are 4-8 steps long.)
 __device__ __forceinline__ double load_fragT_lower(const View &v, int j0, int k0) {
   const int l = lane_id();
   const int j = j0 + (l & 15), k = k0 + (l >> 4);  // A(k, j)
