@@ -347,6 +347,24 @@ def test_dgetrf(m, n, pivot, off):
     assert np.all(Dfull[mask] == SENT)
 
 
+@pytest.mark.parametrize("where", [(0, 0), (3, 0), (5, 2)])
+def test_dgetrf_nan_pivots_as_oracle(where):
+    """A NaN in the pivot column is ranked as the oracle's scan ranks it (kept
+    when it sits at the pivot position, never chosen elsewhere): the same
+    interchanges, and NaNs in the same places of the factor."""
+    note("getrf nan", where)
+    rng = np.random.default_rng(31)
+    C = rng.standard_normal((9, 7))
+    C[where] = np.nan
+    sC, sD = mat(C), p.DMat(9, 7)
+    ipiv = torch.full((7,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_dgetrf_pivot(9, 7, sC, 0, 0, sD, 0, 0, ipiv)
+    D = host(sD)
+    Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=True)
+    assert np.array_equal(ipiv.cpu().numpy(), ipr)
+    assert np.array_equal(D, Dr, equal_nan=True)
+
+
 def test_dgetrf_exact_batched_info_and_errors():
     note("getrf exact/batched")
     rng = np.random.default_rng(90)
