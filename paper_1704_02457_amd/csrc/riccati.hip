@@ -37,6 +37,34 @@ __device__ __forceinline__ int unpad(int x, int nu) {
   return x - 16 * NUB + nu;
 }
 
+// load_tileT split in two: the loads (elements outside the view, or above
+// its diagonal with lower, come from the view's origin) and the masking, so
+// that a group of tiles can be in flight before any is used.
+__device__ __forceinline__ d4 tile_raw(const View &v, int i0, int j0, bool lower) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int o0 = pm_off(v.ai, v.aj, v.cn);
+  d4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + c, j = j0 + g + 4 * r;
+    const bool ok = i < v.rows && j < v.cols && (!lower || i >= j);
+    t[r] = v.p[ok ? pm_off(v.ai + i, v.aj + j, v.cn) : o0];
+  }
+  return t;
+}
+
+__device__ __forceinline__ d4 tile_mask(d4 t, const View &v, int i0, int j0, bool lower) {
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + c, j = j0 + g + 4 * r;
+    t[r] = (i < v.rows && j < v.cols && (!lower || i >= j)) ? t[r] : 0.0;
+  }
+  return t;
+}
+
 template <int NUB, int NXB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ric_trf(RicArgs a) {
   constexpr int NB = NUB + NXB;
@@ -110,6 +138,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 
   for (int n = a.N - 1; n >= 0; --n) {
+    // the constant R and Q blocks of this stage's matrix: their loads go out
+    // first so that they are in flight during the Ct products (placed at
+    // their use, each tile's loads were waited for one after another)
+    d4 RQ[NT];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        if (i < NUB)
+          RQ[tix_up(j, i)] = tile_raw(R, 16 * i, 16 * j, i == j);
+        else if (j >= NUB)
+          RQ[tix_up(j, i)] = tile_raw(Q, 16 * (i - NUB), 16 * (j - NUB), i == j);
+        else
+          RQ[tix_up(j, i)] = zero4();
+      }
+    __builtin_amdgcn_sched_barrier(0);
     // Ct(k, j) = sum_{m >= k} Ln(m,k)^T X^T(m,j)
     d4 T[NT];
     {
@@ -128,9 +172,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int i = 0; i < NB; ++i)
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-          d4 acc;
+          d4 acc = RQ[tix_up(j, i)];
+          if (i < NUB)
+            acc = tile_mask(acc, R, 16 * i, 16 * j, i == j);
+          else if (j >= NUB)
+            acc = tile_mask(acc, Q, 16 * (i - NUB), 16 * (j - NUB), i == j);
           if (i < NUB) {
-            acc = load_tileT(R, 16 * i, 16 * j, i == j);
             if (i == j) {  // identity on the padding rows nu..16*NUB-1
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
@@ -138,10 +185,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 if (p >= nu || q >= nu) acc[r] = (p == q) ? 1.0 : 0.0;
               }
             }
-          } else if (j < NUB) {
-            acc = zero4();
-          } else {
-            acc = load_tileT(Q, 16 * (i - NUB), 16 * (j - NUB), i == j);
+          } else if (j >= NUB) {
             if (i == j) {
               const int nv = min(16, nx - 16 * (j - NUB));
               if (nv < 16) pad_identity(acc, nv);
