@@ -122,3 +122,43 @@ def test_header_compiles_as_c_and_cxx(tmp_path):
         r = subprocess.run([cc, std, "-Wall", "-Werror", "-fsyntax-only", "-I", inc,
                             "-x", "c" if cc == "gcc" else "c++", str(src)], capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("m,n", [(0, 0), (1, 1), (32, 32), (33, 5), (64, 64), (100, 7)])
+def test_smat_memsize_and_create(m, n):
+    """Single precision: 32-float panels, cn = round_up(n, 4), dA after the
+    panels, memsize a multiple of 256 bytes."""
+    L = p.lib()
+    ms = L.blasfeo_memsize_smat(m, n)
+    cn, pm = (n + 3) // 4 * 4, (m + 31) // 32
+    expect = (pm * 32 * cn * 4 + max(m, n) * 4 + 255) // 256 * 256
+    assert ms == expect
+    s = p.blasfeo_smat()
+    L.blasfeo_create_smat(m, n, ctypes.byref(s), ctypes.c_void_p(0x300000))
+    assert (s.m, s.n, s.cn, s.pm, s.memsize, s.use_dA) == (m, n, cn, pm, ms, 0)
+    assert s.pA == 0x300000
+    if pm * cn:
+        assert s.dA == 0x300000 + pm * 32 * cn * 4
+    assert L.blasfeo_memsize_smat(-1, 2) == -1
+
+
+def test_single_batched_argument_errors_before_launch():
+    L = p.lib()
+    s = p.blasfeo_smat()
+    L.blasfeo_create_smat(8, 8, ctypes.byref(s), ctypes.c_void_p(0x100000))
+    r = ctypes.byref(s)
+    g = L.blasfeo_hip_sgemm_nt_batched
+    assert g(-1, 8, 8, 8, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 0, 0, r, 0, 0, None) == -1
+    assert g(1, 9, 8, 8, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 0, 0, r, 0, 0, None) == -6
+    assert g(1, 8, 8, 8, 1.0, r, 0, 0, r, 1, 0, 1.0, r, 0, 0, r, 0, 0, None) == -9
+    assert g(1, 8, 8, 8, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 0, 1, r, 0, 0, None) == -13
+    assert g(1, 8, 8, 8, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 0, 0, None, 0, 0, None) == -16
+    y = L.blasfeo_hip_ssyrk_ln_batched
+    assert y(1, 8, 9, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 0, 0, r, 0, 0, None) == -5
+    assert y(1, 8, 8, 1.0, r, 0, 0, r, 0, 0, 1.0, r, 1, 0, r, 0, 0, None) == -12
+    f = L.blasfeo_hip_spotrf_l_batched
+    assert f(70000, 8, r, 0, 0, r, 0, 0, None, None) == -1
+    assert f(1, -1, r, 0, 0, r, 0, 0, None, None) == -2
+    assert f(1, 8, r, 1, 0, r, 0, 0, None, None) == -3
+    assert f(1, 8, r, 0, 0, r, 0, 1, None, None) == -6
+    assert f(0, 8, r, 0, 0, r, 0, 0, None, None) == 0
