@@ -363,13 +363,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="time only the uniform-batch workload")
     ap.add_argument("--legs", default="uneven,riccati,stacking,single,mixed",
-                    help="comma list of the further workloads to time (uneven, riccati, stacking, mixed)")
+                    help="comma list of the further workloads to time (uneven, riccati, stacking, single, mixed)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent instances would shard by contiguous chunks, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the instances are independent and would shard by contiguous chunks of the batch, "
+              "one chunk per GPU, with no collective on the hot path", file=sys.stderr)
         sys.exit(2)
 
     import torch
