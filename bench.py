@@ -417,11 +417,28 @@ def main():
 
     _, pg = time_events(gemm1, 50, 5, stream)
     _, pp = time_events(potrf1, 50, 5, stream)
+
+    # the other single-instance routines of the path at the same sizes:
+    # syrk_ln 64x64 (k = 64) and trsm_rltn of a 16x64 right-hand side
+    Y1 = p.DMat(64, 64)
+    E1, X1 = p.pack(torch.as_tensor(s["A"][:16], device=dev)), p.DMat(16, 64)
+    p.blasfeo_dpotrf_l(64, S1, 0, 0, L1, 0, 0)
+
+    def syrk1():
+        p.blasfeo_dsyrk_ln(64, 64, 1.0, A1, 0, 0, B1, 0, 0, 1.0, C1, 0, 0, Y1, 0, 0)
+
+    def trsm1():
+        p.blasfeo_dtrsm_rltn(16, 64, 1.0, L1, 0, 0, E1, 0, 0, X1, 0, 0)
+
+    _, ps1 = time_events(syrk1, 50, 5, stream)
+    _, pt1 = time_events(trsm1, 50, 5, stream)
     extra = {
         "single_gemm_nt_64_us": round(float(np.median(pg)) * 1e3, 2),
         "single_gemm_nt_64_gflops": round(2 * 64 ** 3 / (np.median(pg) * 1e-3) / 1e9, 2),
         "single_potrf_l_64_us": round(float(np.median(pp)) * 1e3, 2),
         "single_potrf_l_64_gflops": round(flops_potrf(64) / (np.median(pp) * 1e-3) / 1e9, 2),
+        "single_syrk_ln_64_us": round(float(np.median(ps1)) * 1e3, 2),
+        "single_trsm_rltn_16x64_us": round(float(np.median(pt1)) * 1e3, 2),
         "uniform_kernel_ms_mean": round(kern_ms, 4),
         "uniform_kernel_ms_min": round(float(np.min(per)), 4),
         "uniform_failed_instances": bad,

@@ -167,6 +167,13 @@ __device__ __forceinline__ void diag_inverse_lower(const View &A, int j0,
   V = trtri_tile_upper(Wt, s.inv, s.ulds, s.row);
 }
 
+// One wave per 16-row strip of B, GW strips per workgroup.  For n <= 16 *
+// kTrsmLdsBlocks the inverses of A's diagonal blocks do not depend on the
+// strip: the workgroup's waves form them first, in parallel, into LDS, and
+// every strip then reads them there (otherwise each wave forms each inverse
+// where it needs it).
+constexpr int kTrsmLdsBlocks = 8;
+
 __global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
     int m, int n, double alpha, View A, View B, View D, long long sA,
     long long sB, long long sD) {
@@ -174,11 +181,23 @@ __global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
   B = at_batch(B, sB);
   D = at_batch(D, sD);
   __shared__ WaveLds lds[GW];
+  __shared__ double vinv[kTrsmLdsBlocks][256];  // T-tiles of the diagonal-block inverses
   const int w = wave_id();
+  const int lane = lane_id();
   const int strip = blockIdx.x * GW + w;  // 16 rows of B
-  if (strip * 16 >= m) return;
   WaveLds &s = lds[w];
   const int nb = (n + 15) >> 4;
+  const bool pre = nb <= kTrsmLdsBlocks;
+  if (pre) {
+    for (int j = w; j < nb; j += GW) {
+      d4 V;
+      diag_inverse_lower(A, 16 * j, min(16, n - 16 * j), s, V);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) vinv[j][64 * r + lane] = V[r];
+    }
+    __syncthreads();
+  }
+  if (strip * 16 >= m) return;
   for (int j = 0; j < nb; ++j) {
     d4 z = load_tileT(B, 16 * strip, 16 * j, false);
 #pragma unroll
@@ -189,7 +208,12 @@ __global__ __launch_bounds__(64 * GW) void k_trsm_rltn(
       z = mfma_tn(neg4(a), y, z);
     }
     d4 V;
-    diag_inverse_lower(A, 16 * j, min(16, n - 16 * j), s, V);
+    if (pre) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) V[r] = vinv[j][64 * r + lane];
+    } else {
+      diag_inverse_lower(A, 16 * j, min(16, n - 16 * j), s, V);
+    }
     const d4 y = mfma_tn(V, z, zero4());
     store_tileT(D, 16 * strip, 16 * j, y, false);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
