@@ -74,6 +74,10 @@ def lib():
         L.orc_batch_potrf_potrs.restype = _i
         L.orc_batch_ric_trf.argtypes = [_i, _i, _i, _i, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _i]
         L.orc_batch_ric_trf.restype = _i
+        L.orc_batch_dposv_uniform.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _dp, _ip, _i]
+        L.orc_batch_dposv_uniform.restype = _i
+        L.orc_batch_berr_uniform.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _i]
+        L.orc_batch_berr_uniform.restype = _i
         _lib = L
     return _lib
 
@@ -425,3 +429,36 @@ def batch_dposv_mixed(mats, rhs, tol=1e-12, max_iter=10, prec=FP32, nthreads=0):
                                        iters.ctypes.data_as(_ip), _p(eta), nthreads)
     Xs = [X[offv[i]:offv[i] + int(ns[i]) * nrhs].reshape(int(ns[i]), nrhs, order="F") for i in range(bsz)]
     return Xs, iters[:bsz], eta[:bsz], used
+
+
+def _colmajor_stack(M):
+    """(b, r, c) C-order stack -> contiguous stack of column-major instances."""
+    return np.ascontiguousarray(np.swapaxes(np.asarray(M, dtype=np.float64), 1, 2))
+
+
+def batch_dposv_uniform(A, B, nthreads=0):
+    """Chunk of Cholesky solves of one order: A (b,n,n) (lower triangle
+    read), B (b,n,nrhs) C-order stacks.  Returns (L (b,n,n), X (b,n,nrhs),
+    dA (b,n), info, threads); X of a failed instance is zero."""
+    bsz, n, _ = A.shape
+    nrhs = B.shape[2]
+    Ac, Bc = _colmajor_stack(A), _colmajor_stack(B)
+    L = np.zeros((bsz, n, n))
+    X = np.zeros((bsz, nrhs, n))
+    dA = np.zeros((bsz, n))
+    info = np.zeros(max(bsz, 1), dtype=np.int32)
+    used = lib().orc_batch_dposv_uniform(bsz, n, nrhs, _p(Ac), _p(Bc), _p(L), _p(dA), _p(X),
+                                         info.ctypes.data_as(_ip), nthreads)
+    return np.swapaxes(L, 1, 2), np.swapaxes(X, 1, 2), dA, info[:bsz], used
+
+
+def batch_berr_uniform(A, X, B, nthreads=0):
+    """Largest normwise backward error over the columns of X_b for
+    A_b x = b (lower triangle of A_b read), for a (b,n,n) stack A and
+    (b,n,nrhs) stacks X, B.  Returns (eta (b,), threads)."""
+    bsz, n, _ = A.shape
+    nrhs = B.shape[2]
+    Ac, Xc, Bc = _colmajor_stack(A), _colmajor_stack(X), _colmajor_stack(B)
+    eta = np.zeros(max(bsz, 1))
+    used = lib().orc_batch_berr_uniform(bsz, n, nrhs, _p(Ac), _p(Xc), _p(Bc), _p(eta), nthreads)
+    return eta[:bsz], used

@@ -152,3 +152,49 @@ int orc_batch_dposv_mixed(int batch, const int *n, const long long *offA,
   }
   return used;
 }
+
+double orc_berr(int n, const double *A, int lda, const double *x,
+                const double *b);
+
+/* Uniform-order chunk of Cholesky solves: `batch` instances of order n with
+ * nrhs right-hand sides; instance b's matrix at A + b*n*n (column-major,
+ * lower triangle read), its right-hand sides at B + b*n*nrhs (n x nrhs,
+ * column-major); L, dA and X at the matching offsets (dA: b*n).  Instances
+ * whose factorization fails leave X untouched.  Returns the number of
+ * threads used. */
+int orc_batch_dposv_uniform(int batch, int n, int nrhs, const double *A,
+                            const double *B, double *L, double *dA, double *X,
+                            int *info, int nthreads) {
+  int used = set_threads(nthreads);
+  const size_t sa = (size_t)n * n, sb = (size_t)n * nrhs;
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int b = 0; b < batch; ++b) {
+    const int inf = orc_dpotrf_l(n, A + b * sa, n, L + b * sa, n, dA + (size_t)b * n);
+    info[b] = inf;
+    if (inf == 0 && nrhs > 0)
+      orc_dpotrs_l(n, nrhs, L + b * sa, n, B + b * sb, n, X + b * sb, n);
+  }
+  return used;
+}
+
+/* Normwise backward errors (orc_berr) of `batch` uniform-order instances:
+ * eta[b] = the largest over the nrhs columns of X_b for A_b x = b_c (NaN
+ * propagates).  Layouts as in orc_batch_dposv_uniform.  Returns the number
+ * of threads used. */
+int orc_batch_berr_uniform(int batch, int n, int nrhs, const double *A,
+                           const double *X, const double *B, double *eta,
+                           int nthreads) {
+  int used = set_threads(nthreads);
+  const size_t sa = (size_t)n * n, sb = (size_t)n * nrhs;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b) {
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+      const double e = orc_berr(n, A + b * sa, n, X + b * sb + (size_t)c * n,
+                                B + b * sb + (size_t)c * n);
+      if (e > worst || e != e) worst = e;
+    }
+    eta[b] = worst;
+  }
+  return used;
+}

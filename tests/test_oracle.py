@@ -639,6 +639,63 @@ def test_spotrf_small_integer_exact_in_fp32():
     assert info == 0 and np.array_equal(D.astype(float), L)
 
 
+def test_single_precision_binary32_rounding_pins():
+    """Hand-derived cases whose binary32 result differs from the FP64 result
+    rounded once to binary32, so an oracle that accumulated or multiplied in
+    double would fail them (u32 = 2^-24, ties to even):
+      * 1 + 2^-24 + 2^-24 summed in float, k ascending: each addition is a
+        tie that rounds back to 1, so the sum is 1 (in double: 1 + 2^-23,
+        which is a float); with the small terms first the sum is 1 + 2^-23;
+      * (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24 rounds (tie, to even) to 1 + 2^-11,
+        so -1 + (1 + 2^-12)^2 gives 2^-11 (in double: 2^-11 + 2^-24);
+      * Cholesky of [[1, a], [a, 1 + 2^-11 + 2^-22]], a = 1 + 2^-12: the
+        pivot 1 + 2^-11 + 2^-22 - fl(a^2) = 2^-22 exactly, L11 = 2^-11
+        (in double the pivot is 3 * 2^-24 and L11 = sqrt(3) * 2^-12)."""
+    t = 2.0 ** -24
+    D = oracle.sgemm_nt(np.array([[1.0, 1.0, 1.0]]), np.array([[1.0, t, t]]), np.zeros((1, 1)))
+    assert D[0, 0] == np.float32(1.0)
+    D = oracle.sgemm_nt(np.array([[1.0, 1.0, 1.0]]), np.array([[t, t, 1.0]]), np.zeros((1, 1)))
+    assert D[0, 0] == np.float32(1.0 + 2.0 ** -23)
+    a = 1.0 + 2.0 ** -12
+    D = oracle.sgemm_nt(np.array([[a]]), np.array([[a]]), np.array([[-1.0]]))
+    assert D[0, 0] == np.float32(2.0 ** -11)
+    assert oracle.dgemm_nt(np.array([[a]]), np.array([[a]]), np.array([[-1.0]]))[0, 0] == 2.0 ** -11 + 2.0 ** -24
+    # syrk_ln: the same accumulation in the (1,0) entry; the upper part stays 0
+    A = np.array([[1.0, 1.0, 1.0], [1.0, t, t]])
+    D = oracle.ssyrk_ln(A, A, np.zeros((2, 2)))
+    assert D[1, 0] == np.float32(1.0) and D[0, 0] == np.float32(3.0) and D[0, 1] == 0.0
+    # potrf_l
+    C = np.array([[1.0, a], [a, 1.0 + 2.0 ** -11 + 2.0 ** -22]])
+    L32, info = oracle.spotrf_l(C)
+    assert info == 0
+    assert L32[0, 0] == 1.0 and L32[1, 0] == np.float32(a) and L32[1, 1] == np.float32(2.0 ** -11)
+    L64 = oracle.dpotrf_l(C)[0]
+    assert abs(L64[1, 1] - np.sqrt(3.0) * 2.0 ** -12) <= 2.0 ** -60
+
+
+def test_uniform_chunk_drivers_match_single_calls():
+    """The uniform-order OpenMP drivers used by the full-size parity checks
+    are the per-instance routines, bit for bit."""
+    ns, mats, rhs = synth.conditioned_batch(6, 1e3, seed=40, nrhs=3, sizes=[37] * 6)
+    A, B = np.stack(mats), np.stack(rhs)
+    A[2, 5, 5] = -1.0  # a failing factorization
+    L, X, dA, info, used = oracle.batch_dposv_uniform(A, B, nthreads=3)
+    assert used >= 1
+    for i in range(6):
+        Lr, dAr, ir = oracle.dpotrf_l(A[i])
+        assert info[i] == ir and np.array_equal(L[i], Lr) and np.array_equal(dA[i], dAr)
+        if ir == 0:
+            assert np.array_equal(X[i], oracle.dpotrs_l(Lr, B[i]))
+        else:
+            assert ir == 6 and not X[i].any()
+    eta, _ = oracle.batch_berr_uniform(A, X, B, nthreads=2)
+    for i in (0, 1, 3):
+        assert eta[i] == max(oracle.berr(A[i], X[i][:, c], B[i][:, c]) for c in range(3))
+    Xn = X.copy()
+    Xn[4, 7, 1] = np.nan
+    assert np.isnan(oracle.batch_berr_uniform(A, Xn, B)[0][4])
+
+
 def test_fl16_matches_ieee_binary16():
     """The binary16 rounding against numpy's float16 conversion (an
     independent implementation of the same IEEE definition)."""
