@@ -18,8 +18,9 @@
  *    constant, as the paper requires for the shift/mask address arithmetic.
  *  - The caller owns every byte of memory.  No compute routine allocates
  *    (Appendix A.1.2); the only allocating calls are blasfeo_allocate_dmat /
- *    blasfeo_allocate_dvec (hipMalloc) and plan creation (host memory and a
- *    small device table).
+ *    blasfeo_allocate_dvec / blasfeo_allocate_smat (hipMalloc) and plan
+ *    creation (host memory and a small device table).  Scratch memory of
+ *    the plan executions is a workspace argument, sized by a query.
  *  - All compute routines are asynchronous on the stream set with
  *    blasfeo_hip_set_stream (default: the null stream) or on the stream
  *    argument of the batched entry points (a hipStream_t passed as void*).
@@ -513,36 +514,63 @@ int blasfeo_hip_spotrf_l_batched(int batch, int m,
  *     vec_bytes bytes.
  * The plan sorts the instances into size classes (n <= 16, 32, 48, 64: one
  * wavefront per instance; 64 < n <= 192 and n > 192: one workgroup per
- * instance, largest first), records one kernel launch per class into a hipGraph on the first
- * execution with a given set of pointers, and replays that graph afterwards.
- * Plan creation allocates with hipMalloc a small device table (orders,
- * offsets, class lists) and, for the instances with n > 64, a workspace of
- * 2 KiB per 16-row block (the inverses of the diagonal blocks, kept for the
- * back substitution); execution allocates nothing.
+ * instance, largest first) and launches one kernel per class.
+ * Memory: plan creation allocates with hipMalloc a small device table
+ * (orders, offsets, class lists).  Scratch memory is the caller's: a device
+ * WORKSPACE of the size reported at creation (or by
+ * blasfeo_hip_plan_workspace), 256-byte aligned, holding for the instances
+ * with n > 64 the inverses of the 16x16 diagonal blocks of L (2 KiB per
+ * 16-row block, kept for the back substitution).  Execution and the
+ * mixed-precision call allocate nothing and instantiate nothing; a hipGraph
+ * of the class launches is recorded only by blasfeo_hip_plan_capture.
+ * Concurrent calls on one plan must use distinct workspaces (the workspace
+ * is per call, the plan itself is read-only during execution).
  * ---------------------------------------------------------------------- */
 typedef struct blasfeo_hip_plan blasfeo_hip_plan;
 
 /* batch >= 0 instances of orders n_host[i] in 1..512, nrhs in 0..16.
- * Returns 0 or -i / HIP error; *plan receives the plan. */
+ * Returns 0 or -i / HIP error; *plan receives the plan and
+ * *workspace_bytes (may be NULL) the bytes of the workspace that
+ * blasfeo_hip_dposv_vbatched needs (0 when no order exceeds 64). */
 int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
-                                    blasfeo_hip_plan **plan);
+                                    blasfeo_hip_plan **plan,
+                                    long long *workspace_bytes);
+/* Workspace sizes: fp64_bytes for blasfeo_hip_dposv_vbatched,
+ * mixed_bytes for blasfeo_hip_dposv_mixed_vbatched (0 if the plan cannot
+ * run mixed-precision solves: no right-hand sides, or an order/nrhs whose
+ * working set exceeds the 160 KiB of LDS of a workgroup).  Either pointer
+ * may be NULL.  Returns 0 or -1 (no plan). */
+int blasfeo_hip_plan_workspace(const blasfeo_hip_plan *plan,
+                               long long *fp64_bytes, long long *mixed_bytes);
 /* Byte offsets of every instance (arrays of `batch` entries, may be NULL)
  * and the arena sizes. */
 int blasfeo_hip_plan_layout(const blasfeo_hip_plan *plan, long long *mat_off,
                             long long *vec_off, long long *mat_bytes,
                             long long *vec_bytes);
 /* Factor and solve every instance (device arenas A, L, B, X; info is a
- * device array of `batch` ints, may be NULL).  Asynchronous on `stream`. */
+ * device array of `batch` ints, may be NULL; work: the caller's workspace,
+ * may be NULL when its size is 0).  If a graph was captured for exactly
+ * these seven pointers, it is replayed; otherwise the class kernels are
+ * launched directly.  Allocates nothing.  Asynchronous on `stream`.
+ * Returns 0, -i for bad argument i (-7: workspace missing or not 256-byte
+ * aligned), or a HIP error. */
 int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *plan, const void *A,
                                void *L, const void *B, void *X, int *info,
-                               void *stream);
+                               void *work, void *stream);
+/* Records the class launches of an execution with these pointers into a
+ * hipGraph and instantiates it (replaces any earlier graph of the plan).
+ * A set-up call: it launches nothing. */
+int blasfeo_hip_plan_capture(blasfeo_hip_plan *plan, const void *A, void *L,
+                             const void *B, void *X, int *info, void *work);
 /* Times every candidate launch configuration of every size class on the
  * given data (which is overwritten like an execution) and keeps the fastest
- * (waves per workgroup); synchronizes the stream. */
+ * (waves per workgroup); synchronizes the stream and drops the captured
+ * graph (capture again afterwards). */
 int blasfeo_hip_plan_autotune(blasfeo_hip_plan *plan, const void *A, void *L,
-                              const void *B, void *X, int *info,
+                              const void *B, void *X, int *info, void *work,
                               void *stream);
-/* on = 0 executes with plain launches instead of the captured graph. */
+/* on = 0 never replays a graph (and drops the captured one); on = 1 allows
+ * the replay of a graph recorded by blasfeo_hip_plan_capture. */
 int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);
 /* Writes the chosen configuration of every size class to cfg_out (may be
  * NULL) and returns the number of classes.  Classes 0..3 (n <= 16, 32, 48,
@@ -586,27 +614,27 @@ void blasfeo_hip_plan_destroy(blasfeo_hip_plan *plan);
  * (may be NULL) is 0 for every other instance.  If L is NULL, X_i of a
  * fallen-back instance holds the last iterate (factorization failure: X_i
  * untouched).
- * The first call allocates the plan's workspace for the FP32 factors
- * (blasfeo_hip_plan_enable_mixed; 4 KiB per 16x16 block pair, about
- * 2 n^2 + 32 n floats per instance) with hipMalloc; later calls allocate
- * nothing.  Returns 0, -i for bad argument i (-1 also: plan without
- * right-hand sides, or an order/nrhs whose working set exceeds the 160 KiB
- * of LDS of a workgroup), or a HIP error.  Asynchronous on `stream`.
+ * work is the caller's workspace of blasfeo_hip_plan_workspace's
+ * mixed_bytes (256-byte aligned): the FP64 workspace of the fallback solves,
+ * then the FP32 factor tiles (4 KiB per 16x16 block pair, about
+ * 2 n^2 + 32 n floats per instance).  Allocates nothing.  Returns 0, -i for
+ * bad argument i (-1 also: a plan whose mixed_bytes is 0), or a HIP error.
+ * Asynchronous on `stream`.
  * ---------------------------------------------------------------------- */
 #define BLASFEO_HIP_FP32 1
 #define BLASFEO_HIP_FP16_SCALED 2
-int blasfeo_hip_plan_enable_mixed(blasfeo_hip_plan *plan,
-                                  long long *workspace_bytes);
 int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *plan, int prec,
                                      double tol, int max_iter, const void *A,
                                      const void *B, void *X, void *L,
                                      int *info, int *iters, double *berr,
-                                     int *fallback, void *stream);
+                                     int *fallback, void *work, void *stream);
 /* The FP32 factor L32 of instance i (of S A S, lower triangle, zeros above)
- * from the last mixed-precision call, into the column-major device array
- * dst (leading dimension ldd >= n_i).  Asynchronous on `stream`. */
+ * left in the workspace `work` by the last mixed-precision call that used
+ * it, into the column-major device array dst (leading dimension
+ * ldd >= n_i).  Asynchronous on `stream`. */
 int blasfeo_hip_plan_mixed_factor(const blasfeo_hip_plan *plan, int i,
-                                  float *dst, int ldd, void *stream);
+                                  const void *work, float *dst, int ldd,
+                                  void *stream);
 
 #ifdef __cplusplus
 }

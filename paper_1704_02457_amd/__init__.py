@@ -92,10 +92,12 @@ _SIGS = {
     "blasfeo_hip_dric_trf_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _M, _M, _p, _p]),
     "blasfeo_hip_dric_trs_batched": (_i, [_i, _i, _i, _i, _M, _M, _M, _M, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_pack_dmat_indexed": (_i, [_i, _i, _i, _p, _i, _ll, _p, _p, _i, _p]),
-    "blasfeo_hip_dposv_vbatched_plan": (_i, [_i, _p, _i, ctypes.POINTER(_p)]),
+    "blasfeo_hip_dposv_vbatched_plan": (_i, [_i, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_ll)]),
+    "blasfeo_hip_plan_workspace": (_i, [_p, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
     "blasfeo_hip_plan_layout": (_i, [_p, _p, _p, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
-    "blasfeo_hip_dposv_vbatched": (_i, [_p, _p, _p, _p, _p, _p, _p]),
-    "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_dposv_vbatched": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_capture": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
     "blasfeo_hip_plan_set_config": (_i, [_p, _p, _i]),
@@ -114,9 +116,8 @@ _SIGS = {
     "blasfeo_hip_sgemm_nt_batched": (_i, [_i, _i, _i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i, _p]),
     "blasfeo_hip_ssyrk_ln_batched": (_i, [_i, _i, _i, _f, _S, _i, _i, _S, _i, _i, _f, _S, _i, _i, _S, _i, _i, _p]),
     "blasfeo_hip_spotrf_l_batched": (_i, [_i, _i, _S, _i, _i, _S, _i, _i, _p, _p]),
-    "blasfeo_hip_plan_enable_mixed": (_i, [_p, ctypes.POINTER(_ll)]),
-    "blasfeo_hip_dposv_mixed_vbatched": (_i, [_p, _i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
-    "blasfeo_hip_plan_mixed_factor": (_i, [_p, _i, _p, _i, _p]),
+    "blasfeo_hip_dposv_mixed_vbatched": (_i, [_p, _i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_plan_mixed_factor": (_i, [_p, _i, _p, _p, _i, _p]),
 }
 
 FP32, FP16_SCALED = 1, 2
@@ -583,7 +584,9 @@ class VbPlan:
     Arenas are flat float64 device tensors; instance i's matrix chunk starts
     at element moff[i] of a matrix arena, its n_i x nrhs right-hand sides
     (column-major, leading dimension round_up(n_i, 16)) at element voff[i] of
-    a vector arena.
+    a vector arena.  The workspaces the C calls take are device tensors of
+    ws64_bytes / mixed_bytes bytes; unless one is passed explicitly, the
+    calls use one the object allocates (through torch) on first use.
     """
 
     def __init__(self, ns, nrhs):
@@ -592,8 +595,9 @@ class VbPlan:
         self.nrhs = int(nrhs)
         self.handle = ctypes.c_void_p()
         arr = np.ascontiguousarray(self.ns)
+        wb = ctypes.c_longlong()
         check(lib().blasfeo_hip_dposv_vbatched_plan(len(arr), arr.ctypes.data_as(ctypes.c_void_p), self.nrhs,
-                                                    ctypes.byref(self.handle)))
+                                                    ctypes.byref(self.handle), ctypes.byref(wb)))
         self.moff = np.zeros(max(len(arr), 1), dtype=np.int64)
         self.voff = np.zeros(max(len(arr), 1), dtype=np.int64)
         mb, vb = ctypes.c_longlong(), ctypes.c_longlong()
@@ -602,12 +606,31 @@ class VbPlan:
                                             ctypes.byref(vb)))
         self.moff, self.voff = self.moff[: len(arr)] // 8, self.voff[: len(arr)] // 8
         self.mat_bytes, self.vec_bytes = mb.value, vb.value
+        w64, wmx = ctypes.c_longlong(), ctypes.c_longlong()
+        check(lib().blasfeo_hip_plan_workspace(self.handle, ctypes.byref(w64), ctypes.byref(wmx)))
+        assert w64.value == wb.value
+        self.ws64_bytes, self.mixed_bytes = w64.value, wmx.value
+        self._work = None
 
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib is not None:
             _lib.blasfeo_hip_plan_destroy(h)
             self.handle = ctypes.c_void_p()
+
+    def workspace(self, mixed=False, device="cuda"):
+        """A new device workspace (uint8 tensor) for an FP64 execution or,
+        with mixed=True, for a mixed-precision call."""
+        torch = _torch()
+        nb = self.mixed_bytes if mixed else self.ws64_bytes
+        return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+
+    def _default_work(self, mixed):
+        need = self.mixed_bytes if mixed else self.ws64_bytes
+        if self._work is None or self._work.numel() < need:
+            self._work = None
+            self._work = self.workspace(mixed=mixed)
+        return self._work
 
     def mat_arena(self, fill=None, device="cuda"):
         torch = _torch()
@@ -640,6 +663,23 @@ class VbPlan:
         check(lib().blasfeo_hip_pack_dmat_indexed(len(idx), n, n, At.data_ptr(), n, n * n, off.data_ptr(),
                                                   arena.data_ptr(), 1, _stream()))
 
+    def unpack_class(self, n, idx, arena):
+        """(count, n, n) tensor of the matrices of instances `idx` (all of
+        order n) inside a matrix arena (the indexed unpack)."""
+        torch = _torch()
+        out = torch.empty((len(idx), n, n), dtype=torch.float64, device=arena.device)
+        off = torch.as_tensor(self.moff[idx], dtype=torch.int64, device=arena.device)
+        check(lib().blasfeo_hip_pack_dmat_indexed(len(idx), n, n, out.data_ptr(), n, n * n, off.data_ptr(),
+                                                  arena.data_ptr(), 0, _stream()))
+        return out.transpose(1, 2)
+
+    def dA_class(self, n, idx, arena):
+        """(count, n) inverse diagonals (dA) of instances `idx` of order n."""
+        torch = _torch()
+        cn = (n + 3) // 4 * 4
+        base = torch.as_tensor(self.moff[idx] + (n + 15) // 16 * 16 * cn, dtype=torch.int64, device=arena.device)
+        return arena[base[:, None] + torch.arange(n, device=arena.device)[None, :]]
+
     def rhs_index(self, n, idx):
         """(count, nrhs, n) int64 element indices of the right-hand sides of
         the instances `idx` (all of order n) inside a vector arena."""
@@ -658,38 +698,46 @@ class VbPlan:
         """(count, n, nrhs) blocks of instances `idx` from a vector arena."""
         return arena[self.rhs_index(n, idx)].transpose(1, 2)
 
-    def solve(self, A, L, B, X, info=None, stream=None):
+    def solve(self, A, L, B, X, info=None, work=None, stream=None):
+        w = self._default_work(False) if work is None else work
         return check(lib().blasfeo_hip_dposv_vbatched(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
-                                                      _ptr(info), _stream(stream)))
+                                                      _ptr(info), _ptr(w), _stream(stream)))
 
-    def autotune(self, A, L, B, X, info=None, stream=None):
+    def capture(self, A, L, B, X, info=None, work=None):
+        """Record and instantiate the graph of an execution with these
+        tensors (blasfeo_hip_plan_capture); later solve() calls with the
+        same tensors replay it."""
+        w = self._default_work(False) if work is None else work
+        return check(lib().blasfeo_hip_plan_capture(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
+                                                    _ptr(info), _ptr(w)))
+
+    def autotune(self, A, L, B, X, info=None, work=None, stream=None):
+        w = self._default_work(False) if work is None else work
         return check(lib().blasfeo_hip_plan_autotune(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
-                                                     _ptr(info), _stream(stream)))
+                                                     _ptr(info), _ptr(w), _stream(stream)))
 
     def set_graph(self, on):
         return check(lib().blasfeo_hip_plan_set_graph(self.handle, 1 if on else 0))
 
-    def enable_mixed(self):
-        """Allocate the mixed-precision workspace; returns its size in bytes."""
-        wb = ctypes.c_longlong()
-        check(lib().blasfeo_hip_plan_enable_mixed(self.handle, ctypes.byref(wb)))
-        return wb.value
-
     def solve_mixed(self, A, B, X, iters, berr, fallback, prec=FP32, tol=1e-12, max_iter=10,
-                    L=None, info=None, stream=None):
+                    L=None, info=None, work=None, stream=None):
         """blasfeo_hip_dposv_mixed_vbatched: iters/fallback int32 and berr
         float64 device tensors of `batch` entries; with L (a matrix arena)
         the instances that fall back are re-solved in FP64."""
+        w = self._default_work(True) if work is None else work
         return check(lib().blasfeo_hip_dposv_mixed_vbatched(
             self.handle, int(prec), float(tol), int(max_iter), _ptr(A), _ptr(B), _ptr(X), _ptr(L),
-            _ptr(info), _ptr(iters), _ptr(berr), _ptr(fallback), _stream(stream)))
+            _ptr(info), _ptr(iters), _ptr(berr), _ptr(fallback), _ptr(w), _stream(stream)))
 
-    def mixed_factor(self, i, stream=None):
-        """(n_i, n_i) float32 device tensor: the FP32 factor of S A_i S."""
+    def mixed_factor(self, i, work=None, stream=None):
+        """(n_i, n_i) float32 device tensor: the FP32 factor of S A_i S left
+        in the workspace by the last mixed-precision call."""
         torch = _torch()
         n = int(self.ns[i])
+        w = self._work if work is None else work
         out = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        check(lib().blasfeo_hip_plan_mixed_factor(self.handle, int(i), out.data_ptr(), n, _stream(stream)))
+        check(lib().blasfeo_hip_plan_mixed_factor(self.handle, int(i), _ptr(w), out.data_ptr(), n,
+                                                  _stream(stream)))
         return out.t()  # column-major storage
 
     def set_config(self, cfg):

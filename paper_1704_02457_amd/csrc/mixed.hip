@@ -31,6 +31,7 @@
 //   V_j = U(j,j)^-1, W_j = V_j^T      at tiles 2 NT + j, 2 NT + nb + j
 // with NT = nb (nb + 1) / 2, nb = ceil(n / 16).
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <vector>
 
@@ -731,9 +732,9 @@ static const int kMxFacR = 4;   // block rows per downdate group, factorization
 static const int kMxFacQU = 2;  // steps of the downdate sum loaded together
 static const bool kMxFacZA = true;  // A added after the downdate sum
 
-static int mx_enable(blasfeo_hip_plan *p) {
-  if (p->ws) return 0;
-  if (p->nrhs < 1) return -1;
+int bh::mx_plan_setup(blasfeo_hip_plan *p) {
+  p->mx_ok = false;
+  if (p->nrhs < 1) return 0;
   std::vector<long long> woff(p->batch);
   long long wo = 0;
   int nbmax = 0;
@@ -744,14 +745,13 @@ static int mx_enable(blasfeo_hip_plan *p) {
     wo += 256LL * (nb * (nb + 1) + 2 * nb);
   }
   const size_t lds = mx_lds_bytes(nbmax, p->nrhs);
-  if (lds + sizeof(MxLds<kMxLW>) > 160 * 1024) return -1;
+  if (lds + sizeof(MxLds<kMxLW>) > 160 * 1024) return 0;  // mixed solves unavailable
   std::vector<int> ids(p->batch);
   for (int i = 0; i < p->batch; ++i) ids[i] = i;
   std::stable_sort(ids.begin(), ids.end(),
                    [&](int x, int y) { return p->n[x] > p->n[y]; });
   const size_t nbt = (size_t)std::max(p->batch, 1);
-  hipError_t e = hipMalloc(&p->ws, (size_t)std::max(wo, 1LL) * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&p->d_woff, nbt * sizeof(long long));
+  hipError_t e = hipMalloc(&p->d_woff, nbt * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&p->d_mx_ids, nbt * sizeof(int));
   if (e == hipSuccess && p->batch > 0) {
     e = hipMemcpy(p->d_woff, woff.data(), p->batch * sizeof(long long), hipMemcpyHostToDevice);
@@ -759,36 +759,21 @@ static int mx_enable(blasfeo_hip_plan *p) {
       e = hipMemcpy(p->d_mx_ids, ids.data(), p->batch * sizeof(int), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = mx_prepare<kMxLW, kMxRT>(lds);
-  if (e != hipSuccess) {
-    if (p->ws) (void)hipFree(p->ws);
-    if (p->d_woff) (void)hipFree(p->d_woff);
-    if (p->d_mx_ids) (void)hipFree(p->d_mx_ids);
-    p->ws = nullptr;
-    p->d_woff = nullptr;
-    p->d_mx_ids = nullptr;
-    return (int)e;
-  }
-  p->ws_bytes = wo * (long long)sizeof(float);
+  if (e != hipSuccess) return (int)e;  // the caller destroys the plan
+  p->ws32_bytes = wo * (long long)sizeof(float);
   p->mx_nbmax = nbmax;
+  p->mx_ok = true;
   return 0;
 }
 
 extern "C" {
 
-int blasfeo_hip_plan_enable_mixed(blasfeo_hip_plan *p, long long *workspace_bytes) {
-  if (!p) return -1;
-  const int e = mx_enable(p);
-  if (e < 0) return -1;
-  if (e) return e;
-  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
-  return 0;
-}
-
 int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
                                      int max_iter, const void *A, const void *B,
                                      void *X, void *L, int *info, int *iters,
-                                     double *berr, int *fallback, void *stream) {
-  if (!p || p->nrhs < 1) return -1;
+                                     double *berr, int *fallback, void *work,
+                                     void *stream) {
+  if (!p || !p->mx_ok) return -1;
   if (prec != 1 && prec != 2) return -2;
   if (!(tol >= 0.0)) return -3;
   if (max_iter < 0) return -4;
@@ -799,11 +784,7 @@ int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
   if (!iters) return -10;
   if (!berr) return -11;
   if (!fallback) return -12;
-  {
-    const int e = mx_enable(p);
-    if (e < 0) return -1;
-    if (e) return e;
-  }
+  if (!work || ((uintptr_t)work & 255)) return -13;
   hipStream_t st = (hipStream_t)stream;
   MxArgs a;
   a.ids = p->d_mx_ids;
@@ -815,7 +796,7 @@ int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
   a.A = (const double *)A;
   a.B = (const double *)B;
   a.X = (double *)X;
-  a.ws = p->ws;
+  a.ws = (float *)((char *)work + round256(p->ws64_bytes));
   a.nrhs = p->nrhs;
   a.tol = tol;
   a.max_iter = max_iter;
@@ -831,26 +812,29 @@ int blasfeo_hip_dposv_mixed_vbatched(blasfeo_hip_plan *p, int prec, double tol,
   hipLaunchKernelGGL((k_mx_ir<kMxLW, kMxRT>), dim3(p->batch), dim3(64 * kMxLW), lds, st, a, p->mx_nbmax);
   int e = launch_status();
   if (e) return e;
-  // FP64 solve of the instances that fell back
+  // FP64 solve of the instances that fell back (workspace: the FP64 part)
   if (L) e = launch_all(p, (const double *)A, (double *)L, (const double *)B,
-                        (double *)X, info, st, fallback);
+                        (double *)X, info, (double *)work, st, fallback);
   return e;
 }
 
-int blasfeo_hip_plan_mixed_factor(const blasfeo_hip_plan *p, int i, float *dst,
-                                  int ldd, void *stream) {
-  if (!p || !p->ws) return -1;
+int blasfeo_hip_plan_mixed_factor(const blasfeo_hip_plan *p, int i,
+                                  const void *work, float *dst, int ldd,
+                                  void *stream) {
+  if (!p || !p->mx_ok) return -1;
   if (i < 0 || i >= p->batch) return -2;
-  if (!dst) return -3;
+  if (!work || ((uintptr_t)work & 255)) return -3;
+  if (!dst) return -4;
   const int n = p->n[i];
-  if (ldd < n) return -4;
+  if (ldd < n) return -5;
   long long wo = 0;
   for (int k = 0; k < i; ++k) {
     const int nb = (p->n[k] + 15) / 16;
     wo += 256LL * (nb * (nb + 1) + 2 * nb);
   }
+  const float *ws = (const float *)((const char *)work + round256(p->ws64_bytes));
   hipLaunchKernelGGL(k_mx_factor, dim3((n + 63) / 64, n), dim3(64), 0,
-                     (hipStream_t)stream, p->ws, wo, n, dst, ldd);
+                     (hipStream_t)stream, ws, wo, n, dst, ldd);
   return launch_status();
 }
 

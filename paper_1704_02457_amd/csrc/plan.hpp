@@ -1,5 +1,7 @@
 // Host-side plan of an uneven batch (shared by the FP64 and the
-// mixed-precision solvers).
+// mixed-precision solvers).  The plan owns only host data and a small device
+// table (orders, offsets, class lists); every byte of scratch memory the
+// kernels use comes from the caller's workspace.
 #pragma once
 #include <vector>
 
@@ -23,24 +25,42 @@ struct blasfeo_hip_plan {
   std::vector<Bucket> buckets;
   int use_graph = 1;
   bool have_graph = false;
-  const void *key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void *key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
-  double *wsw = nullptr;          // n > 64: inverse diagonal blocks (W_j tiles)
-  long long *d_wwoff = nullptr;   // per instance offset into wsw (doubles)
-  // mixed-precision solves (allocated on first use)
-  float *ws = nullptr;          // low-precision factors, per instance
-  long long ws_bytes = 0;
-  long long *d_woff = nullptr;  // per instance offset into ws (floats)
+  // Workspace of an FP64 execution: for the instances with n > 64, the
+  // inverses W_j of the diagonal blocks (256 doubles per 16-row block), kept
+  // for the back substitution, at W + wwoff[id] doubles.
+  long long ws64_bytes = 0;
+  long long *d_wwoff = nullptr;
+  // Workspace of a mixed-precision call: the FP64 part above (rounded up to
+  // 256 bytes), then the low-precision factor tiles of every instance at
+  // + woff[id] floats.
+  long long ws32_bytes = 0;
+  long long *d_woff = nullptr;  // per instance offset into the FP32 part (floats)
   int *d_mx_ids = nullptr;      // all instances, longest first
   int mx_nbmax = 0;
+  bool mx_ok = false;           // right-hand sides present and the LDS fits
 };
 
 namespace bh {
-// Launches every size-class kernel of the FP64 solver; with `only` set, an
-// instance id is processed only where only[id] != 0.
+
+inline long long round256(long long b) { return (b + 255) / 256 * 256; }
+
+// Bytes of the workspace of a mixed-precision call.
+inline long long mixed_ws_bytes(const blasfeo_hip_plan *p) {
+  return round256(p->ws64_bytes) + p->ws32_bytes;
+}
+
+// Launches every size-class kernel of the FP64 solver with workspace W; with
+// `only` set, an instance id is processed only where only[id] != 0.
 int launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
-               const double *B, double *X, int *info, hipStream_t st,
-               const int *only = nullptr);
+               const double *B, double *X, int *info, double *W,
+               hipStream_t st, const int *only = nullptr);
+
+// Mixed-precision part of plan creation: the FP32 tile offsets, the
+// longest-first order and the launch attributes (device tables allocated
+// here, never in a compute call).
+int mx_plan_setup(blasfeo_hip_plan *p);
 }  // namespace bh

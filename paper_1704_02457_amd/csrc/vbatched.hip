@@ -18,6 +18,7 @@
 // chunk; its right-hand sides are a column-major n_i x nrhs block with leading
 // dimension round_up(n_i, 16).  The factor L (with its dA) goes to a second
 // arena of the same layout, the solutions to a second vector arena.
+#include <cstdint>
 #include <algorithm>
 #include <vector>
 
@@ -670,7 +671,7 @@ static void launch_small(const VbArgs &a, int vw, hipStream_t st) {
 
 static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Bucket &bk,
                          const double *A, double *L, const double *B, double *X,
-                         int *info, hipStream_t st, const int *only = nullptr) {
+                         int *info, double *W, hipStream_t st, const int *only = nullptr) {
   if (bk.count == 0) return 0;
   VbArgs a;
   a.ids = p->d_ids + bk.first;
@@ -685,7 +686,7 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
   a.nrhs = p->nrhs;
   a.info = info;
   a.only = only;
-  a.wsw = p->wsw;
+  a.wsw = W;
   a.wwoff = p->d_wwoff;
   switch (bk.kind) {
     case 1: launch_small<1>(a, bk.cfg, st); break;
@@ -726,13 +727,13 @@ static int launch_bucket(const blasfeo_hip_plan *p, const blasfeo_hip_plan::Buck
 }
 
 int bh::launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
-                   const double *B, double *X, int *info, hipStream_t st,
-                   const int *only) {
+                   const double *B, double *X, int *info, double *W,
+                   hipStream_t st, const int *only) {
   // the large instances first: they are the longest (LPT)
   for (int pass = 0; pass < 2; ++pass)
     for (const auto &bk : p->buckets) {
       if ((pass == 0) != (bk.kind == 0)) continue;
-      int e = launch_bucket(p, bk, A, L, B, X, info, st, only);
+      int e = launch_bucket(p, bk, A, L, B, X, info, W, st, only);
       if (e) return e;
     }
   return 0;
@@ -741,7 +742,8 @@ int bh::launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
 extern "C" {
 
 int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
-                                    blasfeo_hip_plan **plan) {
+                                    blasfeo_hip_plan **plan,
+                                    long long *workspace_bytes) {
   if (batch < 0) return -1;
   if (batch > 0 && !n_host) return -2;
   if (nrhs < 0 || nrhs > 16) return -3;
@@ -793,6 +795,7 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
       wwo[i] = wtot;
       wtot += 256LL * ((p->n[i] + 15) / 16);
     }
+  p->ws64_bytes = wtot * (long long)sizeof(double);
   std::vector<long long> md(batch), vd(batch);
   for (int i = 0; i < batch; ++i) {
     md[i] = p->moff[i] / 8;
@@ -805,7 +808,6 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
   if (e == hipSuccess) e = hipMalloc(&p->d_voff, nb * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&p->d_ids, nb * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&p->d_wwoff, nb * sizeof(long long));
-  if (e == hipSuccess) e = hipMalloc(&p->wsw, (size_t)std::max(wtot, 1LL) * sizeof(double));
   if (e == hipSuccess && batch > 0)
     e = hipMemcpy(p->d_wwoff, wwo.data(), batch * sizeof(long long), hipMemcpyHostToDevice);
   if (e == hipSuccess && batch > 0) {
@@ -834,11 +836,21 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
       e = hipFuncSetAttribute(kp[k], hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)large_lds_bytes(nbm, nrhs, false));
   }
-  if (e != hipSuccess) {
+  int me = e == hipSuccess ? mx_plan_setup(p) : 0;
+  if (e != hipSuccess || me) {
     blasfeo_hip_plan_destroy(p);
-    return (int)e;
+    return e != hipSuccess ? (int)e : me;
   }
+  if (workspace_bytes) *workspace_bytes = p->ws64_bytes;
   *plan = p;
+  return 0;
+}
+
+int blasfeo_hip_plan_workspace(const blasfeo_hip_plan *p, long long *fp64_bytes,
+                               long long *mixed_bytes) {
+  if (!p) return -1;
+  if (fp64_bytes) *fp64_bytes = p->ws64_bytes;
+  if (mixed_bytes) *mixed_bytes = p->mx_ok ? mixed_ws_bytes(p) : 0;
   return 0;
 }
 
@@ -885,60 +897,78 @@ int blasfeo_hip_plan_config(const blasfeo_hip_plan *p, int *cfg_out) {
   return (int)p->buckets.size();
 }
 
-int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *p, const void *A, void *L,
-                               const void *B, void *X, int *info,
-                               void *stream) {
-  if (!p) return -1;
-  if (p->batch == 0) return 0;
+// Argument checks shared by execution and capture (positions as in
+// blasfeo_hip_dposv_vbatched).
+static int exec_args_ok(const blasfeo_hip_plan *p, const void *A, const void *L,
+                        const void *B, const void *X, const void *W) {
   if (!A) return -2;
   if (!L) return -3;
   if (p->nrhs > 0 && !B) return -4;
   if (p->nrhs > 0 && !X) return -5;
-  hipStream_t st = (hipStream_t)stream;
-  const double *Ad = (const double *)A;
-  double *Ld = (double *)L;
-  const double *Bd = (const double *)B;
-  double *Xd = (double *)X;
-  if (!p->use_graph) return launch_all(p, Ad, Ld, Bd, Xd, info, st);
-  const void *key[5] = {A, L, B, X, info};
-  bool same = p->have_graph;
-  for (int i = 0; i < 5 && same; ++i) same = key[i] == p->key[i];
-  if (!same) {
-    drop_graph(p);
-    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return (int)e;
-    int le = launch_all(p, Ad, Ld, Bd, Xd, info, p->cap);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(p->cap, &g);
-    if (le) {
-      if (g) (void)hipGraphDestroy(g);
-      return le;
-    }
-    if (e != hipSuccess) return (int)e;
-    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return (int)e;
-    }
-    p->graph = g;
-    p->have_graph = true;
-    for (int i = 0; i < 5; ++i) p->key[i] = key[i];
+  if (p->ws64_bytes > 0 && (!W || ((uintptr_t)W & 255))) return -7;
+  return 0;
+}
+
+int blasfeo_hip_plan_capture(blasfeo_hip_plan *p, const void *A, void *L,
+                             const void *B, void *X, int *info, void *work) {
+  if (!p) return -1;
+  if (p->batch == 0) return 0;
+  if (const int e = exec_args_ok(p, A, L, B, X, work)) return e;
+  drop_graph(p);
+  hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return (int)e;
+  const int le = launch_all(p, (const double *)A, (double *)L, (const double *)B,
+                            (double *)X, info, (double *)work, p->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(p->cap, &g);
+  if (le) {
+    if (g) (void)hipGraphDestroy(g);
+    return le;
   }
-  hipError_t e = hipGraphLaunch(p->exec, st);
-  return e == hipSuccess ? 0 : (int)e;
+  if (e != hipSuccess) return (int)e;
+  e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    p->exec = nullptr;
+    return (int)e;
+  }
+  p->graph = g;
+  p->have_graph = true;
+  const void *key[6] = {A, L, B, X, info, work};
+  for (int i = 0; i < 6; ++i) p->key[i] = key[i];
+  return 0;
+}
+
+int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *p, const void *A, void *L,
+                               const void *B, void *X, int *info, void *work,
+                               void *stream) {
+  if (!p) return -1;
+  if (p->batch == 0) return 0;
+  if (const int e = exec_args_ok(p, A, L, B, X, work)) return e;
+  hipStream_t st = (hipStream_t)stream;
+  const void *key[6] = {A, L, B, X, info, work};
+  bool same = p->use_graph && p->have_graph;
+  for (int i = 0; i < 6 && same; ++i) same = key[i] == p->key[i];
+  if (same) {
+    const hipError_t e = hipGraphLaunch(p->exec, st);
+    return e == hipSuccess ? 0 : (int)e;
+  }
+  return launch_all(p, (const double *)A, (double *)L, (const double *)B,
+                    (double *)X, info, (double *)work, st);
 }
 
 int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
-                              const void *B, void *X, int *info, void *stream) {
+                              const void *B, void *X, int *info, void *work,
+                              void *stream) {
   if (!p) return -1;
   if (p->batch == 0) return 0;
-  if (!A || !L || (p->nrhs > 0 && (!B || !X))) return -2;
+  if (const int e = exec_args_ok(p, A, L, B, X, work)) return e;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return -3;
+  if (hipEventCreate(&e0) != hipSuccess) return -8;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
-    return -3;
+    return -8;
   }
   int err = 0;
   for (auto &bk : p->buckets) {
@@ -955,7 +985,7 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
       for (int rep = 0; rep < 3 && !err; ++rep) {
         (void)hipEventRecord(e0, st);
         err = launch_bucket(p, bk, (const double *)A, (double *)L,
-                            (const double *)B, (double *)X, info, st);
+                            (const double *)B, (double *)X, info, (double *)work, st);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
@@ -983,10 +1013,8 @@ void blasfeo_hip_plan_destroy(blasfeo_hip_plan *p) {
   if (p->d_voff) (void)hipFree(p->d_voff);
   if (p->d_ids) (void)hipFree(p->d_ids);
   if (p->cap) (void)hipStreamDestroy(p->cap);
-  if (p->ws) (void)hipFree(p->ws);
   if (p->d_woff) (void)hipFree(p->d_woff);
   if (p->d_mx_ids) (void)hipFree(p->d_mx_ids);
-  if (p->wsw) (void)hipFree(p->wsw);
   if (p->d_wwoff) (void)hipFree(p->d_wwoff);
   delete p;
 }

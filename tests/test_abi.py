@@ -87,11 +87,12 @@ def test_batched_argument_errors_before_launch():
     assert g(1, 64, 64, 64, 1.0, r(A), 0, 0, r(A), 0, 0, 1.0, r(A), 0, 0, r(small), 0, 0, None) == -16
     assert L.blasfeo_hip_dpotrf_l_batched(1, 9, r(small), 0, 0, r(small), 0, 0, None, None) == -3
     # plan entry points without a plan
-    assert L.blasfeo_hip_plan_enable_mixed(None, None) == -1
+    assert L.blasfeo_hip_plan_workspace(None, None, None) == -1
     assert L.blasfeo_hip_dposv_mixed_vbatched(None, 1, 1e-12, 10, None, None, None, None, None,
-                                              None, None, None, None) == -1
-    assert L.blasfeo_hip_plan_mixed_factor(None, 0, None, 1, None) == -1
-    assert L.blasfeo_hip_dposv_vbatched(None, None, None, None, None, None, None) == -1
+                                              None, None, None, None, None) == -1
+    assert L.blasfeo_hip_plan_mixed_factor(None, 0, None, None, 1, None) == -1
+    assert L.blasfeo_hip_dposv_vbatched(None, None, None, None, None, None, None, None) == -1
+    assert L.blasfeo_hip_plan_capture(None, None, None, None, None, None, None) == -1
 
 
 def test_single_routine_errors_recorded():

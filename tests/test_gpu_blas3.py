@@ -278,7 +278,7 @@ def test_dtrsm_rltn(m, n, offs):
 
 def test_dtrsm_rltn_integer_exact():
     note("trsm exact")
-    L, _ = synth.small_integer_factor(48, seed=5, diag=(1.0, 2.0), off=1)
+    L, _ = synth.small_integer_factor(48, seed=5)  # diagonal {1, 2, 4}, off-diagonal -3..3
     X = np.random.default_rng(6).integers(-5, 6, (16, 48)).astype(float)
     sL, sB, sD = mat(L), mat(X @ L.T), p.DMat(16, 48)
     p.blasfeo_dtrsm_rltn(16, 48, 1.0, sL, 0, 0, sB, 0, 0, sD, 0, 0)
@@ -540,10 +540,14 @@ def test_range_space_chain_batched():
         assert_parity(np.tril(S[b]), Sr, n, f"S b={b}")
 
 
-@pytest.mark.parametrize("n", [16, 37, 64, 100])
+@pytest.mark.parametrize("n", [16, 37, 64, 100, 130, 256])
 def test_dpotrf_l_small_integer_exact(n):
+    """A = L L^T with the closed-form L (diagonal {1, 2, 4}, off-diagonal
+    integers -3..3): every partial sum, inverse-block entry and product of
+    the blocked factorization is exactly representable, so L is reproduced
+    bit for bit."""
     note("potrf exact", n)
-    L, A = synth.small_integer_factor(n, seed=n, diag=(1.0, 2.0), off=1)
+    L, A = synth.small_integer_factor(n, seed=n)
     sC, sD = mat(A), p.DMat(n, n)
     p.blasfeo_dpotrf_l(n, sC, 0, 0, sD, 0, 0)
     assert np.array_equal(np.tril(host(sD)), L)
@@ -563,7 +567,7 @@ def test_dpotrf_l_in_place_identity_diagonal():
 @pytest.mark.parametrize("bad", [0, 7, 16, 39])
 def test_dpotrf_l_info_first_failing_pivot(bad):
     note("potrf info", bad)
-    L, A = synth.small_integer_factor(40, seed=21, diag=(1.0, 2.0), off=1)
+    L, A = synth.small_integer_factor(40, seed=21)
     A = A.copy()
     A[bad, bad] -= L[bad, bad] ** 2 + 1.0  # pivot of column `bad` becomes -1
     Lr, _, inf = oracle.dpotrf_l(A)

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from _util import assert_parity, note
+from _util import TOL, assert_parity, note
 
 pytestmark = pytest.mark.gpu
 
@@ -73,7 +73,10 @@ def test_vbatched_graph_replay_and_autotune():
     note("vbatched graph")
     ns = [7, 16, 40, 64, 70, 130, 33, 90]
     plan, mats, rhs, A, L, B, X, info = build(ns, 2, seed=8)
-    plan.solve(A, L, B, X, info)  # captures the graph
+    plan.capture(A, L, B, X, info)  # records and instantiates; launches nothing
+    torch.cuda.synchronize()
+    assert torch.all(torch.isnan(X)) and torch.all(info == -5)
+    plan.solve(A, L, B, X, info)  # replays the graph
     check_all(plan, mats, rhs, L, X, info, 2, "graph first")
     X0 = X.clone()
     for rep in range(3):  # replays, with eager work and syncs in between
@@ -93,8 +96,12 @@ def test_vbatched_graph_replay_and_autotune():
     check_all(plan, mats, rhs, L, X, info, 2, "graph new data")
     plan.autotune(A, L, B, X, info)
     assert len(plan.config()) == 6
-    plan.solve(A, L, B, X, info)
+    plan.solve(A, L, B, X, info)  # the graph was dropped: direct launches
     check_all(plan, mats, rhs, L, X, info, 2, "after autotune")
+    plan.capture(A, L, B, X, info)
+    L.fill_(np.nan)
+    plan.solve(A, L, B, X, info)
+    check_all(plan, mats, rhs, L, X, info, 2, "after autotune, graph")
 
 
 def test_vbatched_failure_is_per_instance():
@@ -148,12 +155,15 @@ def test_vbatched_failure_large_configs(cfg):
     assert [inf[i] for i in bad] == [col + 1 for col in bad.values()]
 
 
-def test_vbatched_full_size_sampled():
+def test_vbatched_full_size_all_instances():
     """The uneven workload at full size (65536 systems, n = 8*U{1..32}, one
-    right-hand side) in the benchmark's configuration; 64 sampled systems
-    are compared element by element with the oracle, and every system is
-    checked through its info code and residual."""
-    note("vbatched full size")
+    right-hand side) in the benchmark's configuration (autotuned launch
+    shapes, captured graph replayed): every system's L (lower), dA and x
+    against the oracle, size class by size class (OpenMP driver), each
+    within 1e-13 n; every info code 0; the oracle's backward error of every
+    GPU solution within (3n+1) u."""
+    note("vbatched full size, all instances")
+    from oracle import parity
     batch = 65536
     ns = synth.uneven_sizes(batch, seed=2)
     plan = p.VbPlan(ns, 1)
@@ -164,31 +174,59 @@ def test_vbatched_full_size_sampled():
     classes = synth.uneven_batch_device(ns, seed=2)
     for n, (idx, An, bn) in classes.items():
         plan.pack_class(n, idx, An, A)
-    for n, (idx, An, bn) in classes.items():
         plan.scatter_rhs(n, idx, bn, B)
     info = torch.full((batch,), -5, dtype=torch.int32, device=DEV)
+    plan.autotune(A, L, B, X, info)
+    plan.capture(A, L, B, X, info)
+    L.fill_(np.nan)
+    X.fill_(np.nan)
+    info.fill_(-5)
     plan.solve(A, L, B, X, info)
     torch.cuda.synchronize()
     assert int((info != 0).sum().item()) == 0
-    rng = np.random.default_rng(1)
-    sample = []
+    w = parity.Worst()
     for n, (idx, An, bn) in classes.items():
-        sample += [(n, int(idx[t]), t) for t in range(min(2, len(idx)))]
-    for n, i, t in sample:
-        Ah = classes[n][1][t].cpu().numpy()
-        Lr, dAr, ir = oracle.dpotrf_l(Ah)
-        Lg = np.tril(p.unpack(plan.dmat(L, i)).cpu().numpy())
-        assert_parity(Lg, Lr, n, f"L n={n} i={i}")
-        bh = plan.rhs(B, i).cpu().numpy()
-        assert_parity(plan.rhs(X, i).cpu().numpy(), oracle.dpotrs_l(Lr, bh), n, f"x n={n} i={i}")
-    # residual of every instance of one size class, computed on the GPU
-    n = 256
-    idx, An, bn = classes[n]
-    Lall = torch.stack([p.unpack(plan.dmat(L, int(i))) for i in idx[:64]])
-    Lall = torch.tril(Lall)
-    R = torch.bmm(Lall, Lall.transpose(1, 2).contiguous()) - An[:64]
-    assert float((torch.linalg.matrix_norm(R) / torch.linalg.matrix_norm(An[:64])).max()) < 256 * 1e-15
-    del rng
+        Lg = plan.unpack_class(n, idx, L).cpu().numpy()
+        dAg = plan.dA_class(n, idx, L).cpu().numpy()
+        Xg = plan.gather_rhs(n, idx, X).cpu().numpy()
+        wc = parity.dposv_chunk(parity.Worst(), An.cpu().numpy(), bn.cpu().numpy()[:, :, None], Lg, dAg, Xg)
+        for k in ("L", "dA", "X"):
+            assert wc[k] <= TOL * n, (n, k, wc[k])
+        assert wc["eta"] <= (3 * n + 1) * 2.0 ** -53, (n, wc["eta"])
+        w.merge(wc)
+    print("[parity] uneven batch", w.as_dict(), flush=True)
+    assert w.instances == batch
+
+
+def test_vbatched_small_integer_exact():
+    """Closed form through every size class: A = L L^T with the small-integer
+    L (diagonal {1, 2, 4}, off-diagonal -3..3) and b = A x with integer x;
+    the factor and the solution come out bit for bit (eager and graph)."""
+    note("vbatched exact")
+    ns = [8, 16, 23, 33, 48, 64, 65, 100, 130, 200, 256]
+    rng = np.random.default_rng(44)
+    facs, mats, xs = [], [], []
+    for i, n in enumerate(ns):
+        Lf, Af = synth.small_integer_factor(n, seed=500 + i)
+        facs.append(Lf)
+        mats.append(Af)
+        xs.append(rng.integers(-4, 5, (n, 2)).astype(float))
+    plan = p.VbPlan(ns, 2)
+    A, L, B, X = plan.mat_arena(fill=np.nan), plan.mat_arena(fill=np.nan), plan.vec_arena(), plan.vec_arena(fill=np.nan)
+    for i, n in enumerate(ns):
+        p.pack(torch.as_tensor(mats[i], device=DEV), out=plan.dmat(A, i))
+        plan.rhs(B, i).copy_(torch.as_tensor(mats[i] @ xs[i], device=DEV))
+    info = torch.full((len(ns),), -5, dtype=torch.int32, device=DEV)
+    for cfg in ([2, 2, 2, 2, 211, 211], [1, 1, 1, 1, 4, 8], [4, 4, 4, 4, 104, 204]):
+        plan.set_config(cfg)
+        L.fill_(np.nan)
+        X.fill_(np.nan)
+        plan.solve(A, L, B, X, info)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        for i, n in enumerate(ns):
+            assert np.array_equal(np.tril(p.unpack(plan.dmat(L, i)).cpu().numpy()), facs[i]), (cfg, n)
+            assert np.array_equal(plan.rhs(X, i).cpu().numpy(), xs[i]), (cfg, n)
 
 
 @pytest.mark.parametrize("cfg", [4, 8, 16, 104, 108, 116, 201, 202, 204, 211, 212, 214])
