@@ -106,7 +106,9 @@ void blasfeo_free_dvec(struct blasfeo_dvec *sx);
  *   pack:   sB[bi:bi+m, bj:bj+n] = A (m-by-n, column-major, leading dim lda)
  *   unpack: B (m-by-n, leading dim ldb) = sA[ai:ai+m, aj:aj+n]
  * A and B are device pointers.  Elements outside the sub-matrix, including
- * panel padding, are not written. */
+ * panel padding, are not written.  A struct whose sub-matrix or sub-vector
+ * does not fit (offset < 0 or past its size) is reported as an error at the
+ * struct's argument position. */
 void blasfeo_pack_dmat(int m, int n, const double *A, int lda,
                        struct blasfeo_dmat *sB, int bi, int bj);
 void blasfeo_unpack_dmat(int m, int n, struct blasfeo_dmat *sA, int ai,

@@ -57,13 +57,19 @@ class Worst:
         return d
 
 
-def dposv_chunk(w, A, B, Lg, dAg, Xg, nthreads=0, gpu_info=None):
+def dposv_chunk(w, A, B, Lg, dAg, Xg, nthreads=0, gpu_info=None, detail=None):
     """One chunk of Cholesky solves of a single order n: A (b,n,n), B, Xg
     (b,n,nrhs), Lg (b,n,n) lower, dAg (b,n).  Records L, dA, X errors against
-    the oracle and the oracle's backward error of the GPU's X ("eta")."""
+    the oracle and the oracle's backward error of the GPU's X ("eta").  With
+    a dict `detail`, also stores the per-instance X errors ("X"), the GPU's
+    and the oracle's own backward errors ("eta", "eta_orc")."""
     t0 = time.perf_counter()
     Lr, Xr, dAr, infr, used = batch_dposv_uniform(A, B, nthreads=nthreads)
     eta, _ = batch_berr_uniform(A, Xg, B, nthreads=nthreads)
+    if detail is not None:
+        detail["eta"] = eta
+        detail["eta_orc"] = batch_berr_uniform(A, Xr, B, nthreads=nthreads)[0]
+        detail["X"] = rel_err(Xg, Xr)
     w.oracle_s += time.perf_counter() - t0
     w.threads = max(w.threads, used)
     assert np.all(infr == 0), "oracle: non-SPD instance in a chunk"

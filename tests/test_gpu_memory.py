@@ -94,8 +94,9 @@ def test_create_dvec_over_caller_memory_with_offsets():
     assert L.blasfeo_hip_get_last_error() == 0
     L.blasfeo_pack_dvec(13, x.data_ptr(), ctypes.byref(v), 28)  # 28 + 13 > 40
     assert L.blasfeo_hip_get_last_error() == -3
+    # an operand outside its vector is reported at the struct's position
     L.blasfeo_unpack_dvec(5, ctypes.byref(v), -1, y.data_ptr())
-    assert L.blasfeo_hip_get_last_error() == -3
+    assert L.blasfeo_hip_get_last_error() == -2
     torch.cuda.synchronize()
     assert np.array_equal(mem.cpu().numpy(), h)
 
@@ -138,7 +139,7 @@ def test_compute_calls_allocate_nothing():
     torch.cuda.synchronize()
     free1 = torch.cuda.mem_get_info()[0]
     assert free0 - free1 < 8 << 20, (free0, free1)
-    assert np.all(fb.cpu().numpy() == 0) and float(berr.max()) <= TOL
+    assert np.all(fb.cpu().numpy() == 0) and float(berr.max()) <= 1e-12  # the refinement target
 
 
 def test_mixed_and_fp64_calls_in_a_captured_graph():
