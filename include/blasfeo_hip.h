@@ -559,6 +559,27 @@ int blasfeo_hip_plan_layout(const blasfeo_hip_plan *plan, long long *mat_off,
 int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *plan, const void *A,
                                void *L, const void *B, void *X, int *info,
                                void *work, void *stream);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, environments that forbid hipMalloc): the
+ * same operation as blasfeo_hip_dposv_vbatched, with the workspace taken
+ * from a fixed device array inside the library instead of a caller's
+ * buffer.  The array holds BLASFEO_HIP_NOALLOC_SCRATCH_BYTES (32 MiB) per
+ * GPU for the life of the process; a plan whose fp64 workspace is larger
+ * (about 16384 diagonal blocks of orders above 64, e.g. 1024 instances of
+ * order 256) is rejected with -1, as is a NULL plan.  The class kernels are
+ * launched directly (a captured graph is not used).  Nothing is allocated:
+ * the array's address is looked up once per device (hipGetSymbolAddress),
+ * by blasfeo_hip_noalloc_init or else by the first call on that device,
+ * with the device current.  Every call on one GPU shares that GPU's array;
+ * calls that overlap in time on one GPU (different streams or threads) race
+ * on it and give undefined results.  The array needs no clearing (each
+ * block's inverse is written before it is read).  Returns 0, -i for bad
+ * argument i, or a HIP error. */
+#define BLASFEO_HIP_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int blasfeo_hip_noalloc_init(void);
+int blasfeo_hip_dposv_vbatched_noalloc(const blasfeo_hip_plan *plan,
+                                       const void *A, void *L, const void *B,
+                                       void *X, int *info, void *stream);
 /* Records the class launches of an execution with these pointers into a
  * hipGraph and instantiates it (replaces any earlier graph of the plan).
  * A set-up call: it launches nothing. */

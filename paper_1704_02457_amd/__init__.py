@@ -97,6 +97,8 @@ _SIGS = {
     "blasfeo_hip_plan_layout": (_i, [_p, _p, _p, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
     "blasfeo_hip_dposv_vbatched": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_capture": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "blasfeo_hip_noalloc_init": (_i, []),
+    "blasfeo_hip_dposv_vbatched_noalloc": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
@@ -702,6 +704,12 @@ class VbPlan:
         w = self._default_work(False) if work is None else work
         return check(lib().blasfeo_hip_dposv_vbatched(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
                                                       _ptr(info), _ptr(w), _stream(stream)))
+
+    def solve_noalloc(self, A, L, B, X, info=None, stream=None):
+        """blasfeo_hip_dposv_vbatched_noalloc: the same solve with the
+        workspace in the library's fixed device array."""
+        return check(lib().blasfeo_hip_dposv_vbatched_noalloc(self.handle, _ptr(A), _ptr(L), _ptr(B), _ptr(X),
+                                                              _ptr(info), _stream(stream)))
 
     def capture(self, A, L, B, X, info=None, work=None):
         """Record and instantiate the graph of an execution with these

@@ -20,6 +20,7 @@
 // arena of the same layout, the solutions to a second vector arena.
 #include <cstdint>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "plan.hpp"
@@ -899,12 +900,18 @@ int blasfeo_hip_plan_config(const blasfeo_hip_plan *p, int *cfg_out) {
 
 // Argument checks shared by execution and capture (positions as in
 // blasfeo_hip_dposv_vbatched).
-static int exec_args_ok(const blasfeo_hip_plan *p, const void *A, const void *L,
-                        const void *B, const void *X, const void *W) {
+static int operands_ok(const blasfeo_hip_plan *p, const void *A, const void *L,
+                       const void *B, const void *X) {
   if (!A) return -2;
   if (!L) return -3;
   if (p->nrhs > 0 && !B) return -4;
   if (p->nrhs > 0 && !X) return -5;
+  return 0;
+}
+
+static int exec_args_ok(const blasfeo_hip_plan *p, const void *A, const void *L,
+                        const void *B, const void *X, const void *W) {
+  if (const int e = operands_ok(p, A, L, B, X)) return e;
   if (p->ws64_bytes > 0 && (!W || ((uintptr_t)W & 255))) return -7;
   return 0;
 }
@@ -955,6 +962,60 @@ int blasfeo_hip_dposv_vbatched(blasfeo_hip_plan *p, const void *A, void *L,
   }
   return launch_all(p, (const double *)A, (double *)L, (const double *)B,
                     (double *)X, info, (double *)work, st);
+}
+
+}  // extern "C"
+
+// Workspace of blasfeo_hip_dposv_vbatched_noalloc: a fixed device array in
+// the code object, one copy per GPU, held until the process ends.  Host code
+// never uses the symbol itself as an address (it is a host-side stand-in):
+// each device's address is read once with hipGetSymbolAddress while that
+// device is current, and only that address is passed to kernels.
+static __device__ __align__(256) double scratch[BLASFEO_HIP_NOALLOC_SCRATCH_BYTES / 8];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device ordinal, null until looked up
+}  // namespace
+
+// Address of this device's scratch array; 0 or a HIP error.
+static int scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!ptr || ((uintptr_t)ptr & 255)) return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+extern "C" {
+
+int blasfeo_hip_noalloc_init(void) {
+  void *ptr = nullptr;
+  return scratch_address(&ptr);
+}
+
+int blasfeo_hip_dposv_vbatched_noalloc(const blasfeo_hip_plan *p, const void *A,
+                                       void *L, const void *B, void *X,
+                                       int *info, void *stream) {
+  if (!p) return -1;
+  if (p->batch == 0) return 0;
+  if (const int e = operands_ok(p, A, L, B, X)) return e;
+  if (p->ws64_bytes > BLASFEO_HIP_NOALLOC_SCRATCH_BYTES) return -1;
+  void *w = nullptr;
+  if (p->ws64_bytes > 0) {
+    if (const int e = scratch_address(&w)) return e;
+  }
+  return launch_all(p, (const double *)A, (double *)L, (const double *)B,
+                    (double *)X, info, (double *)w, (hipStream_t)stream);
 }
 
 int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
