@@ -305,12 +305,11 @@ struct WaveLds {
   double inv[16];
 };
 
-// Scratch of potrf_inv_tile_upper: the pivots, the reciprocals and a padded
-// 16x17 transpose buffer (the pivot rows go through its first 32 doubles).
+// Scratch of potrf_inv_tile_upper: the reciprocals, the pivots and a padded
+// 16x17 transpose buffer (the pivot rows go through its first 128 doubles).
 struct DiagLds {
-  double rowU[16];
-  double rowW[16];
   double inv[16];
+  double piv[16];
   double tr[16 * 17];
 };
 
@@ -332,6 +331,13 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
   return fma(0.5 * r, fma(-d * r, r, 1.0), r);
 }
 
+// Reciprocal square root of a pivot: iv = 1/sqrt(d) if d > 0 (ok), else 0.
+__device__ __forceinline__ void pivot_rsqrt(double d, bool &ok, double &iv) {
+  ok = d > 0.0;
+  const double r = rsqrt_refined(ok ? d : 1.0);
+  iv = ok ? r : 0.0;
+}
+
 // Upper Cholesky factorization of a T-tile together with the inverse of the
 // factor, in one sweep over the 16 pivots.
 //   In:  T holds a symmetric block in its upper triangle (rows <= cols);
@@ -347,12 +353,17 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
 // the T-tile each).  Inside a panel the rank-1 downdates of T and updates of
 // S touch only the panel's rows; the panel's contribution to the rows below
 // is then one rank-4 MFMA for T and one for S (register b of a T-tile is the
-// MFMA operand of rows 4b..4b+3).  The pivot is fetched with readlane, the
-// pivot rows of U and W cross lanes once through LDS, and a wave's LDS
-// operations execute in order, so one wait per pivot suffices.  The chain
-// from one pivot to the next carries only 1/sqrt(d) (rsqrt_refined); the
-// diagonal sqrt(d) is formed for all 16 columns after the sweep.  V is W^T
-// (one LDS transpose at the end).
+// MFMA operand of rows 4b..4b+3).  Each pivot row of U and W crosses lanes
+// through LDS (every lane group writes its own copy, the pivot's group is
+// read back; a wave's LDS operations execute in order).
+// The serial chain from pivot to pivot is shortened by a one-step look-ahead:
+// the next pivot inside the panel, d_{k+1} = T[k+1][k+1] - (T[k][k+1]/U[k][k])^2,
+// is formed from two values read with readlane before this pivot's row
+// broadcast, so its reciprocal square root (rsqrt_refined) runs while the
+// broadcast is in flight.  The product and the downdate are the same
+// roundings as the downdate of the whole row, so the result does not depend
+// on the look-ahead.  The diagonal sqrt(d) is formed for all 16 columns after
+// the sweep; V is W^T (one LDS transpose at the end).
 __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
                                                     DiagLds &s,
                                                     d4 *Wout = nullptr) {
@@ -360,36 +371,58 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
   const int c = l & 15, g = l >> 4;
   int info = 0;
   d4 S = zero4(), W = zero4();
-  double *rowU = s.tr, *rowW = s.tr + 16;
+  double *rowU = s.tr, *rowW = s.tr + 64;  // one 16-entry row per lane group
+  double d = readlane_d(T[0], 0);
+  double t01 = readlane_d(T[0], 1), t11 = readlane_d(T[0], 1 + 16);
+  bool ok;
+  double iv;
+  pivot_rsqrt(d, ok, iv);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * b + kk;
-      const double d = readlane_d(T[b], k + 16 * kk);
-      const bool ok = d > 0.0;
-      const double iv = ok ? rsqrt_refined(d) : 0.0;
       if (!ok && info == 0) info = k + 1;
-      if (l == 0) s.inv[k] = iv;
-      if (l == k) s.rowU[k] = d;  // pivot of column k, for the diagonal below
+      if (l == k) {
+        s.inv[k] = iv;
+        s.piv[k] = d;
+      }
       // row k of U (off the diagonal) and of W, valid in lane group kk
       const double ukc = (c > k) ? T[b] * iv : 0.0;
       const double wkc = (((c == k) ? 1.0 : 0.0) - S[b]) * iv;
+      rowU[16 * g + c] = ukc;
+      rowW[16 * g + c] = wkc;
       const bool mine = g == kk;
-      if (mine) {
-        rowU[c] = ukc;
-        rowW[c] = wkc;
-      }
       T[b] = mine ? ukc : T[b];
       W[b] = mine ? wkc : W[b];
       wave_sync();
+      const double rc = rowU[16 * kk + c];
+      const double rp = rowU[16 * kk + 4 * b + g];
+      const double rw = rowW[16 * kk + c];
+      // the next pivot of this panel while the reads are in flight
+      __builtin_amdgcn_sched_barrier(0);
+      double dn = 0.0, ivn = 0.0;
+      bool okn = true;
+      if (kk < 3) {
+        const double u = t01 * iv;
+        dn = fma(-u, u, t11);
+        pivot_rsqrt(dn, okn, ivn);
+      }
+      __builtin_amdgcn_sched_barrier(0);
       // rank-1 downdate of the panel rows below the pivot (groups g > kk)
-      const double rc = rowU[c];
-      const double rp = rowU[4 * b + g];
-      const double rw = rowW[c];
       const bool below = g > kk;
-      T[b] = (below && c > k) ? T[b] - rp * rc : T[b];
-      S[b] = below ? S[b] + rp * rw : S[b];
+      T[b] = (below && c > k) ? fma(-rp, rc, T[b]) : T[b];
+      S[b] = below ? fma(rp, rw, S[b]) : S[b];
+      wave_sync();
+      if (kk < 3) {
+        d = dn;
+        ok = okn;
+        iv = ivn;
+      }
+      if (kk < 2) {  // T[k+1][k+2] and T[k+2][k+2] for the next look-ahead
+        t01 = readlane_d(T[b], (k + 2) + 16 * (kk + 1));
+        t11 = readlane_d(T[b], (k + 2) + 16 * (kk + 2));
+      }
     }
     if (b < 3) {
       const double ub = T[b], wb = W[b];
@@ -400,15 +433,19 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
         T[r] = Tn[r];
         S[r] = Sn[r];
       }
+      const int k1 = 4 * (b + 1);
+      d = readlane_d(T[b + 1], k1);
+      t01 = readlane_d(T[b + 1], k1 + 1);
+      t11 = readlane_d(T[b + 1], k1 + 1 + 16);
+      pivot_rsqrt(d, ok, iv);
     }
   }
   // the diagonal of U: sqrt(d_c), correctly rounded (exact for squares)
   wave_sync();
-  const double uc = sqrt(s.rowU[c]);
+  const double uc = sqrt(s.piv[c]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) T[r] = (c == g + 4 * r) ? uc : T[r];
   if (Wout) *Wout = W;  // W = L^{-1} = V^T, itself a T-tile
-  wave_sync();
   // V = W^T through a padded LDS transpose
 #pragma unroll
   for (int r = 0; r < 4; ++r) s.tr[(g + 4 * r) * 17 + c] = W[r];
