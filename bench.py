@@ -4,7 +4,8 @@
 Workload timed as `value` (one "step"): the uniform batch -- 16384 independent
 instances of L = chol(Q + B B^T) (n = 64, k = 64) followed by X = E L^{-T}
 with 16 right-hand sides, all in one fused wave-per-instance kernel, inputs
-already resident in HBM in panel-major layout.  Metric: algorithmic GFLOP/s
+already resident in HBM in panel-major layout; a step is one replay of a
+hipGraph holding that call.  Metric: algorithmic GFLOP/s
 (LAPACK Working Note 41 counts) and the fraction of the FP64 peak.
 
 Also reported (under "extra"): the single-instance gemm_nt 64^3 and potrf_l 64
@@ -52,6 +53,58 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+# The paper's own CPU measurements of these routines (single-threaded, one
+# matrix, its BLASFEO HP implementation), quoted with their hardware.  They
+# are context for the oracle baseline, not targets: no GPU figure is in the
+# paper.
+PAPER_CPU = [
+    {"routine": "dpotrf_l, n = 24", "value": "> 10", "unit": "GFLOP/s", "precision": "FP64",
+     "hardware": "Intel Core i7-4800MQ (Haswell) 3.3 GHz, 1 core, AVX2/FMA, peak 52.8 GFLOP/s",
+     "passage": "§5.2 (choice of alternative approaches, Intel Haswell)"},
+    {"routine": "dgemm_nt, n <= 256", "value": "close to peak (52.8)", "unit": "GFLOP/s", "precision": "FP64",
+     "hardware": "Intel Core i7-4800MQ (Haswell) 3.3 GHz, 1 core", "passage": "§1, §5.2 (Intel Haswell)"},
+    {"routine": "dgemm_nt", "value": "up to 95 % of peak (about 27.4 of 28.8)", "unit": "GFLOP/s",
+     "precision": "FP64", "hardware": "Intel Core i7-3520M (Ivy Bridge) 3.6 GHz, 1 core, AVX, peak 28.8 GFLOP/s",
+     "passage": "§5.2 (Intel Ivy-Bridge)"},
+    {"routine": "dgemm_nt", "value": "90 % of peak (about 7.7 of 8.6)", "unit": "GFLOP/s", "precision": "FP64",
+     "hardware": "ARM Cortex A57 (NVIDIA Tegra TX1) 2.15 GHz, 1 core, peak 8.6 GFLOP/s",
+     "passage": "§5.2 (ARM Cortex A57)"},
+    {"routine": "plain C triple loop (the oracle's style), runtime sizes", "value": "about 20 % of peak",
+     "unit": "fraction", "precision": "FP64", "hardware": "Intel Ivy Bridge i3-3420 and Haswell, 1 core",
+     "passage": "Appendix B (numerical experiments)"},
+]
+
+
+def measure_peaks(p, torch, reps=10):
+    """Attainable FP64 matrix-core rate and HBM copy rate on this GPU, with the
+    library's probe kernels (HIP events on the launch stream)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sink = torch.zeros(1024, dtype=torch.float64, device=dev)
+    fl = {}
+
+    def mfma():
+        fl["f"] = p.lib().blasfeo_hip_probe_dmfma(1024, 2000, sink.data_ptr(), stream.cuda_stream)
+
+    _, pm = time_events(mfma, reps, 2, stream)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+
+    def copy():
+        p.check(p.lib().blasfeo_hip_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream))
+
+    _, pc = time_events(copy, reps, 2, stream)
+    del src, dst
+    torch.cuda.empty_cache()
+    if fl["f"] <= 0:
+        raise RuntimeError(f"probe_dmfma failed: {fl['f']}")
+    return {"fp64_mfma_tflops": round(fl["f"] / (np.median(pm) * 1e-3) / 1e12, 2),
+            "hbm_copy_gbs": round(2 * nbytes / (np.median(pc) * 1e-3) / 1e9, 1),
+            "probe": "k_probe_dmfma: 4096 waves x 2000 x 4 independent 16x16x4 FP64 MFMA; "
+                     "k_probe_copy: 1 GiB -> 1 GiB, 16-byte accesses (read + write bytes counted)"}
+
+
 def flops_syrk(n, k):
     return n * (n + 1) * k
 
@@ -81,7 +134,56 @@ def uneven_counts(ns):
     return flops, byts
 
 
-def bench_uneven(p, synth, torch, batch=65536, reps=5):
+def roofline_pair(flops, byts, ms):
+    """Achieved rates of a whole-workload time against both published peaks."""
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+            "gbs_algorithmic": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def cpu_threads():
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_uneven(p, plan, ns, A, L, B, X, per_class=128):
+    """Oracle (potrf + potrs) on a stratified subset of the uneven batch: the
+    first `per_class` instances of every order, timed on the host cores and
+    extrapolated to the whole batch by flops; the GPU's factors and solutions
+    of the subset are compared with the oracle's."""
+    from oracle import parity
+    w = parity.Worst()
+    fl_sub = 0.0
+    for n in sorted(set(int(x) for x in ns)):
+        idx = np.nonzero(ns == n)[0][:per_class]
+        Ah = plan.unpack_class(n, idx, A).cpu().numpy()
+        Bh = plan.gather_rhs(n, idx, B).cpu().numpy()
+        parity.dposv_chunk(w, Ah, Bh, plan.unpack_class(n, idx, L).cpu().numpy(),
+                           plan.dA_class(n, idx, L).cpu().numpy(), plan.gather_rhs(n, idx, X).cpu().numpy(),
+                           nthreads=cpu_threads())
+        fl_sub += len(idx) * (flops_potrf(n) + 2.0 * n * n)
+    fl_all, _ = uneven_counts(ns)
+    # the parity helper also ran the oracle's backward error: time only the
+    # factor + solve with a second pass over the same subset
+    import oracle
+    t = 0.0
+    for n in sorted(set(int(x) for x in ns)):
+        idx = np.nonzero(ns == n)[0][:per_class]
+        Ah = plan.unpack_class(n, idx, A).cpu().numpy()
+        Bh = plan.gather_rhs(n, idx, B).cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.batch_dposv_uniform(Ah, Bh, nthreads=cpu_threads())
+        t += time.perf_counter() - t0
+    gf = fl_sub / t / 1e9
+    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": int(w.threads), "kind": "oracle",
+            "solves_per_s_extrapolated": round(len(ns) / (fl_all / (gf * 1e9)), 1),
+            "sample": f"{w.instances} systems: the first {per_class} of each of the {len(set(ns.tolist()))} orders, "
+                      f"{t:.2f} s, extrapolated to the batch by flops",
+            "parity_subset": {"max_rel_err_L": w["L"], "max_rel_err_X": w["X"], "max_eta": w["eta"],
+                              "instances": w.instances}}
+
+
+def bench_uneven(p, synth, torch, batch=65536, reps=5, cpu=True):
     """The uneven workload: 65536 SPD solves, n = 8*U{1..32}, 1 rhs, through
     a plan (size classes, autotuned launch shapes, captured hipGraph)."""
     ns = synth.uneven_sizes(batch, seed=2)
@@ -104,7 +206,10 @@ def bench_uneven(p, synth, torch, batch=65536, reps=5):
     bad = int((info != 0).sum().item())
     out = {"uneven_ms": round(ms, 3), "uneven_gflops": round(fl / ms / 1e6, 1),
            "uneven_solves_per_s": round(batch / ms * 1e3, 1), "uneven_gbs": round(by / ms / 1e6, 1),
-           "uneven_failed": bad, "uneven_config": [int(x) for x in plan.config()]}
+           "uneven_failed": bad, "uneven_config": [int(x) for x in plan.config()],
+           "uneven_roofline": roofline_pair(fl, by, ms)}
+    if cpu:
+        out["uneven_cpu"] = cpu_uneven(p, plan, ns, A, L, B, X)
     del A, L, B, X, plan
     torch.cuda.empty_cache()
     return out
@@ -117,7 +222,7 @@ def riccati_stage_flops(nx, nu):
     return nm * nx * nx + nm * (nm + 1) * nx + flops_potrf(nm)
 
 
-def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
+def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10, cpu=True):
     """The Riccati workload: 4096 backward recursions, nx=32, nu=8, N=20."""
     d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
     dev = torch.device("cuda:0")
@@ -131,9 +236,26 @@ def bench_riccati(p, synth, torch, batch=4096, nx=32, nu=8, N=20, reps=10):
                                                                 stream), reps, 2, stream)
     ms = float(np.median(per))
     fl = batch * N * riccati_stage_flops(nx, nu)
+    nm = nx + nu
+    # A, B, Q, R, P_N in; N lower (nu+nx)^2 stage factors out
+    by = 8.0 * batch * (2 * nx * nx + nx * nu + nu * nu + nx * nx + N * nm * (nm + 1) / 2)
     out = {"riccati_ms": round(ms, 3), "riccati_gflops": round(fl / ms / 1e6, 1),
            "riccati_recursions_per_s": round(batch / ms * 1e3, 1),
-           "riccati_failed": int((info != 0).sum().item())}
+           "riccati_failed": int((info != 0).sum().item()),
+           "riccati_roofline": roofline_pair(fl, by, ms)}
+    if cpu:
+        from oracle import parity
+        w = parity.Worst()
+        Fg = p.unpack_batch(sF).cpu().numpy().reshape(batch, N, nm, nm)
+        parity.riccati_chunk(w, d, N, Fg, nthreads=cpu_threads())
+        import oracle
+        t0 = time.perf_counter()
+        oracle.batch_ric_trf(d["A"], d["B"], d["Q"], d["R"], d["PN"], N, nthreads=cpu_threads())
+        t = time.perf_counter() - t0
+        out["riccati_cpu"] = {"value": round(fl / t / 1e9, 3), "unit": "GFLOP/s", "cores": int(w.threads),
+                              "kind": "oracle", "recursions_per_s": round(batch / t, 1),
+                              "sample": f"all {batch} recursions, {t:.2f} s",
+                              "parity": {"max_rel_err_F": w["F"], "instances": w.instances}}
     # the solve of the linear-quadratic problem on those factors
     rng = np.random.default_rng(5)
     vb, vr = (torch.as_tensor(rng.standard_normal((batch, N, k)), device=dev) for k in (nx, nu))
@@ -246,7 +368,36 @@ def mixed_fp64_counts(ns, nrhs):
     return float(np.sum(ns ** 3 / 3.0 + ns ** 2 / 2.0 + ns / 6.0 + 2.0 * nrhs * ns ** 2))
 
 
-def bench_mixed(p, synth, torch, batch=16384, nrhs=4, reps=3, conds=(1e2, 1e4, 1e6), fp16_max_cond=1e3):
+def cpu_conditioned(plan, ns, A, L, B, X, nrhs, per_order=16):
+    """Oracle FP64 solves (potrf + potrs) on a stratified subset of the
+    conditioned batch (the first `per_order` systems of every order), timed on
+    the host cores, with the GPU's FP64-plan factors and solutions of the
+    subset compared with the oracle's."""
+    from oracle import parity
+    import oracle
+    w = parity.Worst()
+    fl_sub, t = 0.0, 0.0
+    for n in sorted(set(int(x) for x in ns)):
+        idx = np.nonzero(ns == n)[0][:per_order]
+        Ah = plan.unpack_class(n, idx, A).cpu().numpy()
+        Bh = plan.gather_rhs(n, idx, B).cpu().numpy()
+        parity.dposv_chunk(w, Ah, Bh, plan.unpack_class(n, idx, L).cpu().numpy(),
+                           plan.dA_class(n, idx, L).cpu().numpy(), plan.gather_rhs(n, idx, X).cpu().numpy(),
+                           nthreads=cpu_threads())
+        t0 = time.perf_counter()
+        oracle.batch_dposv_uniform(Ah, Bh, nthreads=cpu_threads())
+        t += time.perf_counter() - t0
+        fl_sub += len(idx) * (flops_potrf(n) + 2.0 * nrhs * n * n)
+    gf = fl_sub / t / 1e9
+    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": int(w.threads), "kind": "oracle",
+            "solves_per_s_extrapolated": round(len(ns) / (mixed_fp64_counts(ns, nrhs) / (gf * 1e9)), 1),
+            "sample": f"{w.instances} systems (the first {per_order} of every order), {t:.2f} s, "
+                      "extrapolated to the batch by flops",
+            "parity_subset": {"max_rel_err_L": w["L"], "max_rel_err_X": w["X"], "max_eta": w["eta"],
+                              "instances": w.instances}}
+
+
+def bench_mixed(p, synth, torch, batch=16384, nrhs=4, reps=3, conds=(1e2, 1e4, 1e6), fp16_max_cond=1e3, cpu=True):
     """The mixed-precision workload: 16384 SPD systems, n ~ U{128..384},
     A = U diag(sigma) U^T with cond in {1e2, 1e4, 1e6}, 4 rhs; the FP32
     (and, for cond <= 1e3, FP16-operand) factor with FP64 refinement to
@@ -282,9 +433,14 @@ def bench_mixed(p, synth, torch, batch=16384, nrhs=4, reps=3, conds=(1e2, 1e4, 1
             tuned = True
         _, per = time_events(lambda: plan.solve(A, L, B, X, info), reps, 1, stream)
         ms64 = float(np.median(per))
+        by64 = float(np.sum(8.0 * (ns * (ns + 1.0) + ns + 2.0 * nrhs * ns)))
         r = {"fp64_ms": round(ms64, 3), "fp64_solves_per_s": round(batch / ms64 * 1e3, 1),
-             "fp64_gflops": round(fl64 / ms64 / 1e6, 1), "fp64_failed": int((info != 0).sum().item())}
+             "fp64_gflops": round(fl64 / ms64 / 1e6, 1), "fp64_failed": int((info != 0).sum().item()),
+             "fp64_roofline": roofline_pair(fl64, by64, ms64)}
+        if cpu and cond == conds[0]:
+            r["fp64_cpu"] = cpu_conditioned(plan, ns, A, L, B, X, nrhs)
         precs = [("fp32", p.FP32)] + ([("fp16", p.FP16_SCALED)] if cond <= fp16_max_cond else [])
+        host = None  # host copies of this condition's matrices, for the oracle's backward errors
         for name, prec in precs:
             def solve():
                 plan.solve_mixed(A, B, X, iters, berr, fb, prec=prec, tol=1e-12, max_iter=10, L=L, info=info)
@@ -294,6 +450,19 @@ def bench_mixed(p, synth, torch, batch=16384, nrhs=4, reps=3, conds=(1e2, 1e4, 1
             f = fb.cpu().numpy()
             be = berr.cpu().numpy()
             ok = f == 0
+            if cpu:
+                # the oracle's backward error of every mixed-precision solution
+                from oracle import parity
+                if host is None:
+                    host = {n: (plan.unpack_class(n, np.nonzero(ns == n)[0], A).cpu().numpy(),
+                                plan.gather_rhs(n, np.nonzero(ns == n)[0], B).cpu().numpy())
+                            for n in sorted(set(int(x) for x in ns))}
+                wm = parity.Worst()
+                for n, (Ah, Bh) in host.items():
+                    parity.eta_chunk(wm, Ah, Bh, plan.gather_rhs(n, np.nonzero(ns == n)[0], X).cpu().numpy(),
+                                     nthreads=cpu_threads())
+                r[f"{name}_oracle_max_berr"] = wm["eta"]
+                r[f"{name}_oracle_checked"] = wm.instances
             r.update({
                 f"{name}_ms": round(ms, 3),
                 f"{name}_solves_per_s": round(batch / ms * 1e3, 1),
@@ -391,10 +560,18 @@ def main():
     info = torch.zeros(B, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
-    def step():
-        p.blasfeo_hip_dsyrk_dpotrf_trsm_batched(B, n, k, nrhs, sA, sQ, sE, sL, sX, info, stream)
+    # one step = one replay of a hipGraph holding the fused batched call
+    gstream = torch.cuda.Stream()
+    gstream.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gstream):
+        p.blasfeo_hip_dsyrk_dpotrf_trsm_batched(B, n, k, nrhs, sA, sQ, sE, sL, sX, info, gstream)
+    torch.cuda.synchronize()
 
-    print("[bench] timing fused syrk+potrf+trsm", file=sys.stderr, flush=True)
+    def step():
+        graph.replay()
+
+    print("[bench] timing fused syrk+potrf+trsm (graph replays)", file=sys.stderr, flush=True)
     wall, per = time_events(step, args.steps, args.warmup, stream)
     bad = int((info != 0).sum().item())
     if bad:
@@ -446,13 +623,18 @@ def main():
         "uniform_failed_instances": bad,
     }
 
+    print("[bench] FP64 matrix-core and HBM copy probes", file=sys.stderr, flush=True)
+    peaks = measure_peaks(p, torch)
+    extra["measured_peaks"] = peaks
+
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
+    cpu_legs = not args.no_cpu
     if "uneven" in legs:
         print("[bench] uneven batch (65536 solves)", file=sys.stderr, flush=True)
-        extra.update(bench_uneven(p, synth, torch))
+        extra.update(bench_uneven(p, synth, torch, cpu=cpu_legs))
     if "riccati" in legs:
         print("[bench] Riccati batch (4096 x N=20)", file=sys.stderr, flush=True)
-        extra.update(bench_riccati(p, synth, torch))
+        extra.update(bench_riccati(p, synth, torch, cpu=cpu_legs))
     if "stacking" in legs:
         print("[bench] stacked potrf_l_mn + range-space chain (16384 x (40 + 8) x 40)", file=sys.stderr, flush=True)
         extra.update(bench_stacking(p, torch))
@@ -461,7 +643,7 @@ def main():
         extra.update(bench_single(p, torch))
     if "mixed" in legs:
         print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
-        extra.update(bench_mixed(p, synth, torch))
+        extra.update(bench_mixed(p, synth, torch, cpu=cpu_legs))
 
     if args.calib_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -501,8 +683,10 @@ def main():
                    "batch": B, "n": n, "k": k, "nrhs": nrhs, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_syrk_potrf_trsm<4>", "bytes_per_instance": by},
+                     "kernel": "k_syrk_potrf_trsm<4>", "bytes_per_instance": by,
+                     "frac_of_measured_copy": round(achieved_gbs / peaks["hbm_copy_gbs"], 4)},
         "cpu_baseline": cpu,
+        "paper_cpu": PAPER_CPU,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)

@@ -659,6 +659,22 @@ int blasfeo_hip_plan_mixed_factor(const blasfeo_hip_plan *plan, int i,
                                   const void *work, float *dst, int ldd,
                                   void *stream);
 
+/* ------------------------------------------------------------------------
+ * Measurement probes (not part of the paper's API): the attainable rates a
+ * roofline of the kernels above is read against, next to the published
+ * peaks.  Both are asynchronous on `stream`; the caller times them.
+ * ---------------------------------------------------------------------- */
+/* Launches `blocks` workgroups of four wavefronts; each wavefront runs
+ * `iters` rounds of four independent 16x16x4 FP64 matrix-core products.
+ * sink: a device double per block (written only if the accumulated value
+ * is -1, i.e. never for these inputs).  Returns the flop count of the
+ * launch (> 0), -i for bad argument i, or a HIP error code. */
+long long blasfeo_hip_probe_dmfma(int blocks, int iters, double *sink, void *stream);
+/* dst = src, `bytes` bytes (a multiple of 16; both 16-byte aligned device
+ * pointers), 16-byte accesses in a grid-stride loop.  Returns 0, -i, or a
+ * HIP error code. */
+int blasfeo_hip_probe_copy(const void *src, void *dst, long long bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,8 @@ _SIGS = {
     "blasfeo_hip_dposv_vbatched": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_capture": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_noalloc_init": (_i, []),
+    "blasfeo_hip_probe_dmfma": (ctypes.c_longlong, [_i, _i, _p, _p]),
+    "blasfeo_hip_probe_copy": (_i, [_p, _p, ctypes.c_longlong, _p]),
     "blasfeo_hip_dposv_vbatched_noalloc": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
