@@ -140,6 +140,16 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
   for (int j = 0; j < NB; ++j) {
     const int nv = FULL ? 16 : min(16, m - 16 * j);
     d4 &D = T[tix_up(j, j)];
+    // Diagonal blocks of L are written as whole 128-byte panel columns: the
+    // part above the diagonal is rewritten with the values it already holds
+    // (read while the block is factored), because a line written only partly
+    // costs the memory a read-modify-write.  Only where every line of the
+    // block lies inside the matrix (FULL); elsewhere the store is masked.
+    d4 Lold;
+    if (FULL) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Lold[r] = bload(rL, vo, j * pL + 8 * (256 * j + 64 * r));
+    }
     if (!FULL && nv < 16) pad_identity(D, nv);
     d4 V;
     const int inf = potrf_inv_tile_upper(D, V, s);
@@ -149,7 +159,9 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * j + c, col = 16 * j + g + 4 * r;
-      if ((FULL || (row < m && col < m)) && c >= g + 4 * r)
+      if (FULL)
+        bstore(rL, vo, j * pL + 8 * (256 * j + 64 * r), c >= g + 4 * r ? D[r] : Lold[r]);
+      else if (row < m && col < m && c >= g + 4 * r)
         bstore(rL, vo, j * pL + 8 * (256 * j + 64 * r), D[r]);
     }
 #pragma unroll
