@@ -331,10 +331,12 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
   return fma(0.5 * r, fma(-d * r, r, 1.0), r);
 }
 
-// Reciprocal square root of a pivot: iv = 1/sqrt(d) if d > 0 (ok), else 0.
+// Reciprocal square root of a pivot: iv = 1/sqrt(d) if d > 0 (ok), else 0
+// (for d <= 0 or NaN the refinement yields NaN or an infinity, which the
+// final selection drops).
 __device__ __forceinline__ void pivot_rsqrt(double d, bool &ok, double &iv) {
   ok = d > 0.0;
-  const double r = rsqrt_refined(ok ? d : 1.0);
+  const double r = rsqrt_refined(d);
   iv = ok ? r : 0.0;
 }
 
@@ -409,10 +411,14 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
         pivot_rsqrt(dn, okn, ivn);
       }
       __builtin_amdgcn_sched_barrier(0);
-      // rank-1 downdate of the panel rows below the pivot (groups g > kk)
+      // rank-1 downdate of the panel rows below the pivot (groups g > kk).
+      // rp is zero in the other groups (it is row k of U left of column
+      // k + 1), so S needs no selection: its rows up to the pivot's are not
+      // used again.  T keeps one, so that a non-finite pivot row cannot
+      // reach the finished rows through 0 * inf.
       const bool below = g > kk;
       T[b] = (below && c > k) ? fma(-rp, rc, T[b]) : T[b];
-      S[b] = below ? fma(rp, rw, S[b]) : S[b];
+      S[b] = fma(rp, rw, S[b]);
       wave_sync();
       if (kk < 3) {
         d = dn;
