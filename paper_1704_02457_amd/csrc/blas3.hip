@@ -272,7 +272,7 @@ __global__ __launch_bounds__(64 * GW) void k_potrf_l(
       }
       pad_identity(t, nv);
       d4 v;
-      const int inf = potrf_inv_tile_upper(t, v, s.d);
+      const int inf = potrf_inv_tile_upper(t, v, s.d, nullptr, (nv + 3) >> 2);
       if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
       if (stacked) {
         const d4 ub = mfma_tn(v, tb, zero4());
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(64) void k_potrf_reg(
     }
     pad_identity(Dj, nv);
     d4 V;
-    const int inf = potrf_inv_tile_upper(Dj, V, s);
+    const int inf = potrf_inv_tile_upper(Dj, V, s, nullptr, (nv + 3) >> 2);
     if (inf && inf0 == 0) inf0 = 16 * j + inf;
     if (stacked) {
       const d4 ub = mfma_tn(V, tb, zero4());

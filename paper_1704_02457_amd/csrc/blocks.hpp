@@ -366,9 +366,13 @@ __device__ __forceinline__ void pivot_rsqrt(double d, bool &ok, double &iv) {
 // roundings as the downdate of the whole row, so the result does not depend
 // on the look-ahead.  The diagonal sqrt(d) is formed for all 16 columns after
 // the sweep; V is W^T (one LDS transpose at the end).
+// With np < 4 (the caller's block holds the identity in rows and columns
+// 4 np..15, as pad_identity leaves it) only the first np panels are swept;
+// the rest of U, V and W is the identity.
 __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
                                                     DiagLds &s,
-                                                    d4 *Wout = nullptr) {
+                                                    d4 *Wout = nullptr,
+                                                    int np = 4) {
   const int l = lane_id();
   const int c = l & 15, g = l >> 4;
   int info = 0;
@@ -381,6 +385,10 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
   pivot_rsqrt(d, ok, iv);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
+    if (b >= np) {  // identity rows
+      W[b] = (c == g + 4 * b) ? 1.0 : 0.0;
+      continue;
+    }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * b + kk;
@@ -430,7 +438,7 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
         t11 = readlane_d(T[b], (k + 2) + 16 * (kk + 2));
       }
     }
-    if (b < 3) {
+    if (b < 3 && b + 1 < np) {
       const double ub = T[b], wb = W[b];
       const d4 Tn = mfma(-ub, ub, T);
       const d4 Sn = mfma(ub, wb, S);
@@ -445,6 +453,10 @@ __device__ __forceinline__ int potrf_inv_tile_upper(d4 &T, d4 &V,
       t11 = readlane_d(T[b + 1], k1 + 1 + 16);
       pivot_rsqrt(d, ok, iv);
     }
+  }
+  if (l >= 4 * np && l < 16) {
+    s.inv[l] = 1.0;
+    s.piv[l] = 1.0;
   }
   // the diagonal of U: sqrt(d_c), correctly rounded (exact for squares)
   wave_sync();

@@ -152,7 +152,7 @@ __device__ __forceinline__ void fused_instance(const FusedArgs &a, long long b,
     }
     if (!FULL && nv < 16) pad_identity(D, nv);
     d4 V;
-    const int inf = potrf_inv_tile_upper(D, V, s);
+    const int inf = potrf_inv_tile_upper(D, V, s, nullptr, (nv + 3) >> 2);
     if (inf && info == 0) info = 16 * j + inf;
     if (l < nv) bstore(rL, vo, dA_off + 8 * 16 * j, s.inv[l]);
     // store L(j,j) (lower part of the diagonal block)

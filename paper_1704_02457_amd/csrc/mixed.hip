@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64 * LW) void k_mx_fac(MxArgs a) {
       d4 T = t32_to_t64(acc[0], tr);
       pad_identity(T, min(16, n - 16 * j));
       d4 V, W;
-      const int inf = potrf_inv_tile_upper(T, V, s.diag, &W);
+      const int inf = potrf_inv_tile_upper(T, V, s.diag, &W, (min(16, n - 16 * j) + 3) >> 2);
       if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
       const f4 u32 = t64_to_t32(T, tr);
       const f4 v32 = t64_to_t32(V, tr);

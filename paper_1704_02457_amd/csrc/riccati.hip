@@ -119,7 +119,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const int nv = min(16, nx - 16 * j);
       if (nv < 16) pad_identity(D, nv);
       d4 V;
-      const int inf = potrf_inv_tile_upper(D, V, s);
+      const int inf = potrf_inv_tile_upper(D, V, s, nullptr, (nv + 3) >> 2);
       if (inf && info == 0) info = 1000 * (a.N + 1) + 16 * j + inf;
 #pragma unroll
       for (int i = j + 1; i < NXB; ++i) T[tix_up(j, i)] = mfma_tn(V, T[tix_up(j, i)], zero4());
@@ -202,7 +202,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int j = 0; j < NB; ++j) {
       d4 &D = T[tix_up(j, j)];
       d4 V;
-      const int inf = potrf_inv_tile_upper(D, V, s);
+      // rows past the control block's nu (or the state block's nx) are identity
+      const int nvj = j < NUB ? min(16, nu - 16 * j) : min(16, nx - 16 * (j - NUB));
+      const int inf = potrf_inv_tile_upper(D, V, s, nullptr, (nvj + 3) >> 2);
       if (inf && info == 0) {
         // report the pivot as an index of the unpadded stage matrix
         const int pv = unpad<NUB>(16 * j + inf - 1, nu);

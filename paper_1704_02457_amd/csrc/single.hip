@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_spotrf_l(int m, SView C, SView D, float
       d4 T = st32_to_t64(t, s.tr);
       pad_identity(T, nv);
       d4 V, W;
-      const int inf = potrf_inv_tile_upper(T, V, s.d, &W);
+      const int inf = potrf_inv_tile_upper(T, V, s.d, &W, (nv + 3) >> 2);
       if (inf && l == 0 && s.info == 0) s.info = 16 * j + inf;
       // L(j,j) = U^T: row 16j + c, column 16j + g + 4r holds U[g + 4r][c]
 #pragma unroll
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(64) void k_spotrf_reg(int m, SView C, SView D, floa
     d4 Dj = st32_to_t64(T[tix_up(j, j)], s.tr);
     pad_identity(Dj, nv);
     d4 V;
-    const int inf = potrf_inv_tile_upper(Dj, V, s.d);
+    const int inf = potrf_inv_tile_upper(Dj, V, s.d, nullptr, (nv + 3) >> 2);
     if (inf && inf0 == 0) inf0 = 16 * j + inf;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

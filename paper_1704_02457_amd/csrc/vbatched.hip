@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64 * VW) void k_vb_small(VbArgs a) {
     d4 &D = T[tix_up(j, j)];
     if (nv < 16) pad_identity(D, nv);
     d4 V;
-    const int inf = potrf_inv_tile_upper(D, V, s, &Wk[j]);
+    const int inf = potrf_inv_tile_upper(D, V, s, &Wk[j], (nv + 3) >> 2);
     if (inf && info == 0) info = 16 * j + inf;
     if (l < nv) bstore(rL, vo, 8 * (int)(panel_doubles + 16 * j), s.inv[l]);
 #pragma unroll
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
       }
       pad_identity(t0, nv);
       d4 V, W;
-      const int inf = potrf_inv_tile_upper(t0, V, s, &W);
+      const int inf = potrf_inv_tile_upper(t0, V, s, &W, (nv + 3) >> 2);
       if (inf && l == 0 && sinfo == 0) sinfo = 16 * j + inf;
       pm_stT(L, j, j, t0, true);
       if (l < nv) dAb[16 * j + l] = s.inv[l];
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
       // block j
       pad_identity(t00, min(16, n - 16 * j));
       d4 V0, W0;
-      int inf = potrf_inv_tile_upper(t00, V0, s, &W0);
+      int inf = potrf_inv_tile_upper(t00, V0, s, &W0, (min(16, n - 16 * j) + 3) >> 2);
       if (inf && l == 0 && sinfo == 0) sinfo = 16 * j + inf;
       pm_stT(L, j, j, t00, true);
       if (l < min(16, n - 16 * j)) dAb[16 * j + l] = s.inv[l];
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(3))) vo
         const int nv1 = min(16, n - 16 * (j + 1));
         pad_identity(t11, nv1);
         d4 V1, W1;
-        inf = potrf_inv_tile_upper(t11, V1, s, &W1);
+        inf = potrf_inv_tile_upper(t11, V1, s, &W1, (nv1 + 3) >> 2);
         if (inf && l == 0 && sinfo == 0) sinfo = 16 * (j + 1) + inf;
         pm_stT(L, j + 1, j + 1, t11, true);
         if (l < nv1) dAb[16 * (j + 1) + l] = s.inv[l];
