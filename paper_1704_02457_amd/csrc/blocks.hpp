@@ -14,7 +14,7 @@
 //   * loading the TRANSPOSE of a 16x16 block of a panel-major matrix into a
 //     T-tile reads, for register r, the 64 consecutive doubles
 //     [64r, 64r+64) of the block's 16 panel columns: one contiguous 512-byte
-//     wave transaction (§4.3's "data is read along panels").
+//     wave transaction (the panel-wise reads of §4.3).
 // The kernels therefore work on transposed blocks: a lower factor L is held
 // as its transpose U = L^T, and every trailing update, triangular solve and
 // product is a chain of MFMAs on register tiles.

@@ -207,14 +207,16 @@ __global__ __launch_bounds__(256) void k_sgemm_nt(int m, int n, int k, float alp
   // scheduling barriers keep the compiler from moving them (or the waits for
   // them) back.  Rows of A or B beyond m or n only reach rows or columns of
   // the accumulators that are never stored, so only the k index is masked,
-  // on the B fragment, after the MFMAs.
+  // on both fragments (a non-finite element read in place of a missing
+  // column would otherwise reach every output through 0 * inf).
   const int g = lane_id() >> 4;
   float fa[4] = {0.f, 0.f, 0.f, 0.f}, fb[4] = {0.f, 0.f, 0.f, 0.f};
   if (k > 0) {  // k == 0: A and B are empty views without storage
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      fa[t] = sload_frag_raw(A, i0 + 16 * t, 0);
+      const float xa = sload_frag_raw(A, i0 + 16 * t, 0);
       const float x = sload_frag_raw(B, j0 + 16 * t, 0);
+      fa[t] = g < k ? xa : 0.f;
       fb[t] = g < k ? x : 0.f;
     }
   }
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void k_sgemm_nt(int m, int n, int k, float alp
     const bool kin = k0 + 4 + g < k;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      fa[t] = na[t];
+      fa[t] = kin ? na[t] : 0.f;
       fb[t] = kin ? nb[t] : 0.f;
     }
   }

@@ -125,6 +125,27 @@ def test_sgemm_nt(m, n, k, offs):
     assert np.all(D[mask] == np.float32(SENT))
 
 
+@pytest.mark.parametrize("k", [5, 7, 30])
+def test_sgemm_nt_nonfinite_origin_stays_in_its_row(k):
+    """k not a multiple of 4 and an infinite A(ai, aj): only row 0 of D is
+    non-finite, as in the oracle; every other row matches it."""
+    note("sgemm_nt inf origin", k)
+    m, n, ai, aj = 40, 33, 3, 5
+    rng = np.random.default_rng(k)
+    A, B, C = (rng.uniform(-1, 1, s).astype(np.float32) for s in ((m, k), (n, k), (m, n)))
+    A[0, 0] = np.inf
+    sA = sentinel(ai + m, aj + k)
+    p.spack(dev(A), out=sA, bi=ai, bj=aj)
+    sB, sC, sD = smat(B), smat(C), sentinel(m, n)
+    p.blasfeo_sgemm_nt(m, n, k, 1.0, sA, ai, aj, sB, 0, 0, 1.0, sC, 0, 0, sD, 0, 0)
+    D = host(sD)
+    ref = oracle.sgemm_nt(A, B, C, 1.0, 1.0)
+    assert np.all(np.isfinite(D[1:])) and np.all(~np.isfinite(ref[0]))
+    assert np.array_equal(np.isinf(D[0]) & (np.sign(D[0]) == np.sign(ref[0])), np.isinf(ref[0]))
+    err = np.abs(D[1:].astype(np.float64) - ref[1:])
+    assert np.all(err <= gemm_bound(A[1:], B, C[1:], 1.0, 1.0)), err.max()
+
+
 def test_sgemm_nt_integer_exact_and_in_place():
     """Small integers: every product and partial sum is exact in binary32."""
     note("sgemm_nt exact")
