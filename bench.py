@@ -537,6 +537,11 @@ def main():
                     help="comma list of the further workloads to time (uneven, riccati, stacking, single, mixed)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--tune-cache", default=os.environ.get(
+                        "BLASFEO_HIP_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "blasfeo_hip",
+                                                               "tune.txt")),
+                    help="tuning-cache file of the plans' autotuner: loaded before the legs, saved after them "
+                         "('' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -629,6 +634,7 @@ def main():
 
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     cpu_legs = not args.no_cpu
+    tune_loaded = p.tune_cache_load(args.tune_cache) if args.tune_cache else 0
     if "uneven" in legs:
         print("[bench] uneven batch (65536 solves)", file=sys.stderr, flush=True)
         extra.update(bench_uneven(p, synth, torch, cpu=cpu_legs))
@@ -644,6 +650,13 @@ def main():
     if "mixed" in legs:
         print("[bench] mixed precision vs FP64 (16384 x n in [128,384], 4 rhs)", file=sys.stderr, flush=True)
         extra.update(bench_mixed(p, synth, torch, cpu=cpu_legs))
+
+    if args.tune_cache and ({"uneven", "mixed"} & legs):
+        os.makedirs(os.path.dirname(os.path.abspath(args.tune_cache)), exist_ok=True)
+        p.tune_cache_save(args.tune_cache)
+    ent, hits, miss = p.tune_cache_stats()
+    extra["tuning_cache"] = {"path": args.tune_cache or None, "entries_loaded": tune_loaded,
+                             "entries": ent, "classes_from_cache": hits, "classes_timed": miss}
 
     if args.calib_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

@@ -585,13 +585,40 @@ int blasfeo_hip_dposv_vbatched_noalloc(const blasfeo_hip_plan *plan,
  * A set-up call: it launches nothing. */
 int blasfeo_hip_plan_capture(blasfeo_hip_plan *plan, const void *A, void *L,
                              const void *B, void *X, int *info, void *work);
-/* Times every candidate launch configuration of every size class on the
- * given data (which is overwritten like an execution) and keeps the fastest
- * (waves per workgroup); synchronizes the stream and drops the captured
- * graph (capture again afterwards). */
+/* Picks the launch configuration of every size class (the tile and panel
+ * shapes of the project's own autotuner, not a paper passage).  A class
+ * found in the process's tuning cache (below) takes the cached value and is
+ * not run; every other class has each candidate configuration timed on the
+ * given data (which is overwritten like an execution), keeps the fastest
+ * (waves per workgroup, kernel variant) and enters it into the cache.
+ * Synchronizes the stream when anything was timed and drops the captured
+ * graph (capture again afterwards).  Returns 0, -1 for a NULL plan, the
+ * argument errors of blasfeo_hip_dposv_vbatched, or a HIP error. */
 int blasfeo_hip_plan_autotune(blasfeo_hip_plan *plan, const void *A, void *L,
                               const void *B, void *X, int *info, void *work,
                               void *stream);
+/* Tuning cache: one process-wide table (guarded by a mutex) from a size
+ * class to its configuration.  The key is the device's architecture name
+ * and compute-unit count, the class kind (1..4: n <= 16, 32, 48, 64; 0: the
+ * n > 64 classes), nrhs, the number of instances and their smallest,
+ * largest and summed order; a plan over the same orders on the same kind
+ * of device therefore skips the timing runs.  The file is plain text, one
+ * entry per line: "arch cus kind nrhs count nmin nmax nsum cfg ms" ('#'
+ * starts a comment line; ms is the time measured for cfg, informative).
+ *   _load: merges the file's entries into the table; returns their number,
+ *          0 if the file does not exist, -1 for a NULL path, -2 for a
+ *          malformed line or an invalid configuration (then nothing is
+ *          merged).
+ *   _save: writes the whole table (through a temporary file renamed into
+ *          place); returns the number of entries, -1 for a NULL path, -2 for
+ *          an I/O error.
+ *   _clear: empties the table and zeroes the counters.
+ *   _stats: entries in the table, lookups that hit and that missed (any
+ *          pointer may be NULL). */
+int blasfeo_hip_tune_cache_load(const char *path);
+int blasfeo_hip_tune_cache_save(const char *path);
+int blasfeo_hip_tune_cache_clear(void);
+int blasfeo_hip_tune_cache_stats(long long *entries, long long *hits, long long *misses);
 /* on = 0 never replays a graph (and drops the captured one); on = 1 allows
  * the replay of a graph recorded by blasfeo_hip_plan_capture. */
 int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *plan, int on);

@@ -103,6 +103,10 @@ _SIGS = {
     "blasfeo_hip_dposv_vbatched_noalloc": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_autotune": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "blasfeo_hip_plan_set_graph": (_i, [_p, _i]),
+    "blasfeo_hip_tune_cache_load": (_i, [ctypes.c_char_p]),
+    "blasfeo_hip_tune_cache_save": (_i, [ctypes.c_char_p]),
+    "blasfeo_hip_tune_cache_clear": (_i, []),
+    "blasfeo_hip_tune_cache_stats": (_i, [ctypes.POINTER(_ll), ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
     "blasfeo_hip_plan_config": (_i, [_p, _p]),
     "blasfeo_hip_plan_set_config": (_i, [_p, _p, _i]),
     "blasfeo_hip_plan_destroy": (None, [_p]),
@@ -156,6 +160,34 @@ def check(code):
     if code != 0:
         raise HipError(f"blasfeo_hip error {code}: {lib().blasfeo_hip_strerror(code).decode()}")
     return code
+
+
+def tune_cache_load(path):
+    """Merge a tuning-cache file into the library's table; returns the
+    number of entries read (0 if the file does not exist)."""
+    r = lib().blasfeo_hip_tune_cache_load(os.fsencode(path))
+    if r < 0:
+        raise HipError(f"tuning cache {path}: malformed (code {r})")
+    return r
+
+
+def tune_cache_save(path):
+    """Write the library's tuning table to `path`; returns the entry count."""
+    r = lib().blasfeo_hip_tune_cache_save(os.fsencode(path))
+    if r < 0:
+        raise HipError(f"tuning cache {path}: cannot write (code {r})")
+    return r
+
+
+def tune_cache_clear():
+    lib().blasfeo_hip_tune_cache_clear()
+
+
+def tune_cache_stats():
+    """(entries, hits, misses) of the library's tuning table."""
+    e, h, m = _ll(0), _ll(0), _ll(0)
+    lib().blasfeo_hip_tune_cache_stats(ctypes.byref(e), ctypes.byref(h), ctypes.byref(m))
+    return e.value, h.value, m.value
 
 
 def check_last():

@@ -3,6 +3,7 @@
 // table (orders, offsets, class lists); every byte of scratch memory the
 // kernels use comes from the caller's workspace.
 #pragma once
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -23,6 +24,7 @@ struct blasfeo_hip_plan {
     int cfg;    // small: waves per block (1, 2, 4); large: waves per instance (4, 8)
   };
   std::vector<Bucket> buckets;
+  std::vector<int> ids;  // host copy of the class lists (d_ids)
   int use_graph = 1;
   bool have_graph = false;
   const void *key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -58,6 +60,26 @@ inline long long mixed_ws_bytes(const blasfeo_hip_plan *p) {
 int launch_all(const blasfeo_hip_plan *p, const double *A, double *L,
                const double *B, double *X, int *info, double *W,
                hipStream_t st, const int *only = nullptr);
+
+// Launch configuration values valid for a size class (kind 1..4: small
+// kernel; 0: n > 64).
+inline bool tune_cfg_valid(int kind, int cfg) {
+  if (kind >= 1 && kind <= 4) return cfg == 1 || cfg == 2 || cfg == 4;
+  if (kind != 0) return false;
+  return cfg == 1 || cfg == 2 || cfg == 4 || cfg == 8 || cfg == 16 || cfg == 104 ||
+         cfg == 108 || cfg == 116 || cfg == 201 || cfg == 202 || cfg == 204 ||
+         cfg == 211 || cfg == 212 || cfg == 214;
+}
+
+// What identifies a size class in the tuning cache.
+struct TuneKey {
+  std::string arch;
+  int cus = 0, kind = 0, nrhs = 0, count = 0, nmin = 0, nmax = 0;
+  long long nsum = 0;
+};
+int tune_key_device(TuneKey &k);  // fills arch and cus of the current device
+bool tune_lookup(const TuneKey &k, int *cfg);
+void tune_store(const TuneKey &k, int cfg, float ms);
 
 // Mixed-precision part of plan creation: the FP32 tile offsets, the
 // longest-first order and the launch attributes (device tables allocated

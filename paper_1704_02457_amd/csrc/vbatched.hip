@@ -789,6 +789,7 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
     const int nbmax = big.empty() ? 0 : (p->n[big[0]] + 15) / 16;
     p->buckets.push_back({0, first, (int)big.size(), nbmax, part == 0 ? 2 : 1});
   }
+  p->ids = ids;
   std::vector<long long> wwo(batch, 0);
   long long wtot = 0;
   for (int i = 0; i < batch; ++i)
@@ -873,12 +874,7 @@ int blasfeo_hip_plan_set_graph(blasfeo_hip_plan *p, int on) {
   return 0;
 }
 
-static bool cfg_valid(int kind, int cfg) {
-  if (kind) return cfg == 1 || cfg == 2 || cfg == 4;
-  return cfg == 1 || cfg == 2 || cfg == 4 || cfg == 8 || cfg == 16 || cfg == 104 ||
-         cfg == 108 || cfg == 116 || cfg == 201 || cfg == 202 || cfg == 204 ||
-         cfg == 211 || cfg == 212 || cfg == 214;
-}
+static bool cfg_valid(int kind, int cfg) { return tune_cfg_valid(kind, cfg); }
 
 int blasfeo_hip_plan_set_config(blasfeo_hip_plan *p, const int *cfg, int count) {
   if (!p) return -1;
@@ -1031,9 +1027,27 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
     (void)hipEventDestroy(e0);
     return -8;
   }
-  int err = 0;
+  TuneKey key;
+  int err = tune_key_device(key) ? -8 : 0;
   for (auto &bk : p->buckets) {
-    if (bk.count == 0) continue;
+    if (bk.count == 0 || err) continue;
+    key.kind = bk.kind;
+    key.nrhs = p->nrhs;
+    key.count = bk.count;
+    key.nmin = 1 << 30;
+    key.nmax = 0;
+    key.nsum = 0;
+    for (int t = 0; t < bk.count; ++t) {
+      const int nn = p->n[p->ids[bk.first + t]];
+      key.nmin = std::min(key.nmin, nn);
+      key.nmax = std::max(key.nmax, nn);
+      key.nsum += nn;
+    }
+    int cached = 0;
+    if (tune_lookup(key, &cached)) {
+      bk.cfg = cached;
+      continue;
+    }
     const int cands_small[3] = {1, 2, 4};
     const int cands_large[11] = {1, 2, 4, 8, 104, 108, 201, 202, 204, 211, 212};
     const int *cands = bk.kind ? cands_small : cands_large;
@@ -1059,6 +1073,7 @@ int blasfeo_hip_plan_autotune(blasfeo_hip_plan *p, const void *A, void *L,
       }
     }
     bk.cfg = best_cfg;
+    if (!err) tune_store(key, best_cfg, best / 2);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -163,3 +163,53 @@ def test_single_batched_argument_errors_before_launch():
     assert f(1, 8, r, 1, 0, r, 0, 0, None, None) == -3
     assert f(1, 8, r, 0, 0, r, 0, 1, None, None) == -6
     assert f(0, 8, r, 0, 0, r, 0, 0, None, None) == 0
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache's file format: load merges, save writes every entry
+    (one line each, sorted), malformed lines and invalid configurations are
+    rejected without merging anything, a missing file is an empty cache."""
+    p.tune_cache_clear()
+    assert p.tune_cache_stats() == (0, 0, 0)
+    assert p.tune_cache_load(str(tmp_path / "none.txt")) == 0
+    src = tmp_path / "in.txt"
+    src.write_text("# comment\n"
+                   "gfx950:sramecc+:xnack- 256 0 4 8192 193 384 2359296 202 7.5000\n"
+                   "\n"
+                   "  gfx950:sramecc+:xnack- 256 2 1 900 17 32 22000 4 0.0500\n"
+                   "gfx950:sramecc+:xnack- 256 0 4 8192 128 192 1310720 211 3.2500")
+    assert p.tune_cache_load(str(src)) == 3
+    assert p.tune_cache_stats()[0] == 3
+    out = tmp_path / "out.txt"
+    assert p.tune_cache_save(str(out)) == 3
+    lines = out.read_text().splitlines()
+    assert lines[0].startswith("#") and len(lines) == 4
+    assert sorted(lines[1:]) == sorted([
+        "gfx950:sramecc+:xnack- 256 0 4 8192 193 384 2359296 202 7.5000",
+        "gfx950:sramecc+:xnack- 256 2 1 900 17 32 22000 4 0.0500",
+        "gfx950:sramecc+:xnack- 256 0 4 8192 128 192 1310720 211 3.2500"])
+    # the same key again replaces its value; a new key adds one
+    upd = tmp_path / "upd.txt"
+    upd.write_text("gfx950:sramecc+:xnack- 256 2 1 900 17 32 22000 2 0.0400\n"
+                   "gfx942 304 1 1 10 8 16 120 1 0.0100\n")
+    assert p.tune_cache_load(str(upd)) == 2
+    assert p.tune_cache_save(str(out)) == 4
+    assert "gfx950:sramecc+:xnack- 256 2 1 900 17 32 22000 2 0.0400" in out.read_text()
+    # rejected files leave the table as it was
+    for bad in ["gfx950 256 0 4 10 100 200 1500 3 1.0\n",      # cfg 3 invalid for n > 64
+                "gfx950 256 2 1 10 17 32 250 8 1.0\n",         # cfg 8 invalid for a small class
+                "gfx950 256 7 1 10 17 32 250 1 1.0\n",         # no class kind 7
+                "gfx950 256 0 4 10 100\n",                     # too few fields
+                "gfx950 256 0 4 10 100 200 1500 202 1.0 9\n",  # trailing field
+                "gfx950 256 0 4 10 200 100 1500 202 1.0\n",    # nmax < nmin
+                "gfx950 256 0 4 0 100 200 1500 202 1.0\n",     # no instances
+                "x" * 600 + "\n"]:                            # longer than a line may be
+        f = tmp_path / "bad.txt"
+        f.write_text("gfx9 1 1 0 1 1 1 1 1 0.1\n" + bad)
+        with pytest.raises(p.HipError):
+            p.tune_cache_load(str(f))
+        assert p.tune_cache_stats()[0] == 4
+    with pytest.raises(p.HipError):
+        p.tune_cache_save(str(tmp_path / "no_such_dir" / "x.txt"))
+    p.tune_cache_clear()
+    assert p.tune_cache_stats() == (0, 0, 0)

@@ -104,6 +104,37 @@ def test_vbatched_graph_replay_and_autotune():
     check_all(plan, mats, rhs, L, X, info, 2, "after autotune, graph")
 
 
+def test_vbatched_autotune_cache(tmp_path):
+    """A plan over the same orders takes every class's configuration from
+    the tuning cache (saved to a file and loaded back) without running
+    anything, and solves correctly with it."""
+    note("vbatched tune cache")
+    ns = [7, 16, 40, 64, 70, 130, 33, 90, 200, 250]
+    classes = 5  # n <= 16, 33..48, 49..64, 65..192, > 192
+    p.tune_cache_clear()
+    plan, mats, rhs, A, L, B, X, info = build(ns, 2, seed=8)
+    plan.autotune(A, L, B, X, info)
+    cfg = plan.config()
+    assert p.tune_cache_stats() == (classes, 0, classes)
+    path = str(tmp_path / "tune.txt")
+    assert p.tune_cache_save(path) == classes
+    p.tune_cache_clear()
+    assert p.tune_cache_load(path) == classes
+    plan2, mats, rhs, A, L, B, X, info = build(ns, 2, seed=9)
+    plan2.autotune(A, L, B, X, info)
+    torch.cuda.synchronize()
+    assert p.tune_cache_stats() == (classes, classes, 0)
+    assert torch.all(torch.isnan(L)) and torch.all(info == -5), "a cached autotune launched work"
+    assert list(plan2.config()) == list(cfg)
+    plan2.solve(A, L, B, X, info)
+    check_all(plan2, mats, rhs, L, X, info, 2, "cached configuration")
+    # a different batch of orders is a different key: it is timed
+    plan3, mats, rhs, A, L, B, X, info = build(ns[:-1], 2, seed=9)
+    plan3.autotune(A, L, B, X, info)
+    assert p.tune_cache_stats()[2] >= 1
+    p.tune_cache_clear()
+
+
 def test_vbatched_failure_is_per_instance():
     note("vbatched failure")
     ns = [20, 64, 100, 48, 150]
