@@ -325,7 +325,27 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
                         stream)
     m4 = float(np.median(t4))
     del sG, sLU, sLQ
-    return {"gelqf_64_batch_ms": round(m4, 4),
+    # the blocked LU (orders above 64): 2048 independent 256 x 256 matrices,
+    # and one 256 x 256 matrix alone (latency)
+    nb, bb = 256, 2048
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(15)
+    sG = p.pack_batch(torch.randn((bb, nb, nb), dtype=torch.float64, device=dev, generator=gen))
+    sLU = p.DMatBatch(bb, nb, nb)
+    ipb = torch.zeros((bb, nb), dtype=torch.int32, device=dev)
+    infb = torch.zeros(bb, dtype=torch.int32, device=dev)
+    _, t5 = time_events(lambda: p.blasfeo_hip_dgetrf_batched(bb, nb, nb, sG, 0, 0, sLU, 0, 0, 1, ipb, infb, stream),
+                        reps, 1, stream)
+    m5 = float(np.median(t5))
+    _, t6 = time_events(lambda: p.blasfeo_hip_dgetrf_batched(1, nb, nb, sG, 0, 0, sLU, 0, 0, 1, ipb, infb, stream),
+                        reps, 2, stream)
+    m6 = float(np.median(t6))
+    del sG, sLU
+    return {"getrf_pivot_256_batch_ms": round(m5, 3),
+            "getrf_pivot_256_batch_gflops": round(bb * (2.0 / 3.0) * nb ** 3 / m5 / 1e6, 1),
+            "getrf_pivot_256_batch_config": f"{bb} x {nb}x{nb}, blocked (panels of 16, MFMA trailing update)",
+            "getrf_pivot_256_single_us": round(m6 * 1e3, 1),
+            "gelqf_64_batch_ms": round(m4, 4),
             "gelqf_64_batch_gflops": round(batch * (4.0 / 3.0) * nl ** 3 / m4 / 1e6, 1),
             "getrf_pivot_64_batch_ms": round(m3, 4),
             "getrf_pivot_64_batch_gflops": round(batch * (2.0 / 3.0) * nl ** 3 / m3 / 1e6, 1),

@@ -184,14 +184,17 @@ void blasfeo_dpotrf_l_mn(int m, int n, struct blasfeo_dmat *sC, int ci,
                          int cj, struct blasfeo_dmat *sD, int di, int dj);
 
 /* getrf (§5.2.2; the API's getrf_pivot / getrf_nopivot): LU of the m-by-n
- * matrix C (m, n <= 64) into D: unit lower L below the diagonal, U on and
+ * matrix C (m, n <= 256) into D: unit lower L below the diagonal, U on and
  * above it, sD->dA[k] = 1/U[k][k].  With pivoting, row k is swapped with
  * row ipiv[k] >= k (0-based, the first row of largest magnitude in column
  * k) before step k; ipiv is a device array of min(m,n) ints.  A zero pivot
  * does not stop the factorization (as in LAPACK; the batched entry point
- * reports it in info).  Errors: -1 m, -2 n (outside 0..64), -3 C, -6 D (or
- * a NULL dA), -9 a NULL ipiv.  C and D may be the same matrix at the same
- * offsets. */
+ * reports it in info).  m, n <= 64: unblocked, the oracle's operations in
+ * its order (identical bits); larger: blocked by panels of 16 columns with
+ * the trailing update on the matrix cores (§5.2.2's blocked form; the
+ * factors agree to rounding).  Errors: -1 m, -2 n (outside 0..256), -3 C,
+ * -6 D (or a NULL dA), -9 a NULL ipiv.  C and D may be the same matrix at
+ * the same offsets. */
 void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
                           int cj, struct blasfeo_dmat *sD, int di, int dj,
                           int *ipiv);
@@ -295,10 +298,10 @@ int blasfeo_hip_dgemm_nn_batched(int batch, int m, int n, int k,
                                  int cj, const struct blasfeo_dmat *sD,
                                  int di, int dj, void *stream);
 
-/* Uniform batch of getrf (pivot = 1 with partial pivoting, 0 without):
- * ipiv[b*min(m,n) + k] (device; may be NULL without pivoting), info[b] =
- * 0 or k+1 for the first zero pivot U[k][k] (device; may be NULL).  Returns
- * 0, -i for bad argument i, or a HIP error code. */
+/* Uniform batch of getrf (pivot = 1 with partial pivoting, 0 without;
+ * m, n <= 256 as above): ipiv[b*min(m,n) + k] (device; may be NULL without
+ * pivoting), info[b] = 0 or k+1 for the first zero pivot U[k][k] (device;
+ * may be NULL).  Returns 0, -i for bad argument i, or a HIP error code. */
 int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sC, int ci, int cj,
                                const struct blasfeo_dmat *sD, int di, int dj,

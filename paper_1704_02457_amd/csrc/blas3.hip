@@ -499,6 +499,238 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   if (info && l == 0) info[b] = inf;
 }
 
+// ---------------------------------------------------------------- getrf, blocked
+// LU with partial pivoting of an m-by-n matrix with max(m, n) > 64 (up to
+// 256), blocked by panels of 16 columns as in §5.2.2 (getrf: a panel
+// factorization, the row interchanges, the triangular solve for the block
+// row of U, then the trailing matrix updated by a gemm), one workgroup of 256
+// threads per instance, D updated in place after a copy of C:
+//   (a) the panel's rows k0..m-1 are held one per thread (16 registers);
+//       for each of its columns the pivot is the first row of largest
+//       magnitude (a wave argmax on DPP, then over the four waves through
+//       LDS), row k and the pivot row trade places through LDS, which also
+//       broadcasts the pivot row, and the rows below form their multipliers
+//       and update the panel's remaining columns;
+//   (b) the panel's interchanges are applied to every column outside the
+//       panel (one thread per column, in order);
+//   (c) U12 = L11^{-1} A12 by forward substitution with the unit lower L11,
+//       one thread per column, the result also kept in LDS;
+//   (d) A22 -= L21 U12 on the f64 MFMA, one wave per 16x16 block of A22
+//       (the transposed product, so that each lane's accumulator is one
+//       element of D).
+// These are the oracle's operations with the updates of the columns right
+// of a panel delayed to (d), so the factors agree to rounding and the
+// interchanges agree wherever the pivot candidates differ by more than the
+// rounding; on data whose every intermediate value is exact the results are
+// the oracle's bit for bit.
+constexpr int kGetrfBigT = 256;  // threads per instance = the largest m
+constexpr int kGetrfBigN = 256;  // the largest n
+
+template <bool PIVOT>
+__global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4))) void k_getrf_big(int m, int n, View C, View D, double *dA,
+                                                          int *ipiv, int *info, long long sC,
+                                                          long long sD, long long sdA, long long sip) {
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *dAb = dA ? dA + b * sdA : nullptr;
+  int *ipb = ipiv ? ipiv + b * sip : nullptr;
+  __shared__ double u12[16][kGetrfBigN + 1];  // block row of U right of the panel
+  __shared__ double l11[16][17];              // the panel's unit lower block
+  __shared__ double prow[2][2][16];           // [parity][row k, pivot row][column]
+  __shared__ double wkey[2][4];
+  __shared__ int wpos[2][4];
+  __shared__ int spiv[16];
+  const int w = wave_id();
+  const int mn = min(m, n);
+  // D through a buffer descriptor: a 32-bit byte offset per access (the
+  // panels holding rows 0..ai+m-1 of D)
+  const brsrc rD = make_rsrc(D.p, 8LL * ((D.ai + m + 15) & ~15) * D.cn);
+  auto doff = [&](int i, int j) { return 8 * (int)pm_off(D.ai + i, D.aj + j, D.cn); };
+  auto dld = [&](int i, int j) { return bload(rD, doff(i, j), 0); };
+  auto dst = [&](int i, int j, double x) { bstore(rD, doff(i, j), 0, x); };
+  for (int e = threadIdx.x; e < m * n; e += kGetrfBigT) {
+    const int i = e % m, j = e / m;
+    dst(i, j, C.p[pm_off(C.ai + i, C.aj + j, C.cn)]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __syncthreads();
+  int inf = 0;
+  for (int k0 = 0; k0 < mn; k0 += 16) {
+    const int wd = min(16, mn - k0);
+    // the thread index passes through an empty asm each panel, so that what
+    // is derived from it is recomputed here rather than kept live (and
+    // spilled) across the whole panel loop
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int l = t & 63;
+    // (a) the panel, one row per thread
+    const int row = k0 + t;
+    const bool live = row < m;
+    const int rc = min(row, m - 1);
+    double r[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double x = dld(rc, min(k0 + c, n - 1));  // clamped: no branch
+      r[c] = (live && c < wd) ? x : 0.0;
+    }
+    for (int kk = 0; kk < wd; ++kk) {
+      const int k = k0 + kk;
+      const int par = kk & 1;
+      double v = r[0];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) v = kk == e ? r[e] : v;
+      int pt = kk;  // panel-local index of the pivot row
+      if (PIVOT) {
+        // the oracle's scan keeps row k unless a later row is strictly
+        // larger: a NaN in row k wins, a NaN elsewhere never does
+        const double av = __builtin_isnan(v) ? (t == kk ? __builtin_inf() : -0.5) : fabs(v);
+        double key = (live && t >= kk) ? av : -1.0;
+        int kp = t;
+        argmax_step<0x111, 0xf>(key, kp);  // row_shr:1
+        argmax_step<0x112, 0xf>(key, kp);  // row_shr:2
+        argmax_step<0x114, 0xf>(key, kp);  // row_shr:4
+        argmax_step<0x118, 0xf>(key, kp);  // row_shr:8: lane 15 of a row holds its best
+        argmax_step<0x142, 0xa>(key, kp);  // row_bcast:15 into rows 1 and 3
+        argmax_step<0x143, 0xc>(key, kp);  // row_bcast:31 into rows 2 and 3
+        if (l == 63) {
+          wkey[par][w] = key;
+          wpos[par][w] = kp;
+        }
+        __syncthreads();
+        double bk = wkey[par][0];
+        pt = wpos[par][0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          const double k2 = wkey[par][q];
+          const int p2 = wpos[par][q];
+          if (k2 > bk || (k2 == bk && p2 < pt)) {
+            bk = k2;
+            pt = p2;
+          }
+        }
+      }
+      // rows k and k0 + pt trade places; prow[par][1] is the pivot row
+      if (t == kk) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) prow[par][0][c] = r[c];
+      }
+      if (t == pt) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) prow[par][1][c] = r[c];
+      }
+      __syncthreads();
+      if (pt != kk && (t == kk || t == pt)) {
+        const int src = t == kk ? 1 : 0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) r[c] = prow[par][src][c];
+      }
+      const double piv = prow[par][1][kk];
+      const double invp = 1.0 / piv;
+      if (t == 0) {
+        spiv[kk] = k0 + pt;
+        if (ipb) ipb[k] = k0 + pt;
+        if (dAb) dAb[k] = invp;
+        if (piv == 0.0 && inf == 0) inf = k + 1;
+      }
+      if (live && t > kk) {
+        double vk = r[0];
+#pragma unroll
+        for (int e = 1; e < 16; ++e) vk = kk == e ? r[e] : vk;
+        const double mult = vk * invp;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double upd = r[c] - mult * prow[par][1][c];
+          r[c] = c == kk ? mult : (c > kk && c < wd) ? upd : r[c];
+        }
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < wd) dst(row, k0 + c, r[c]);
+    }
+    if (t < wd) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) l11[t][c] = r[c];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    // (b) the interchanges in the columns outside the panel
+    if (PIVOT) {
+      const int j = t;
+      if (j < n && (j < k0 || j >= k0 + wd)) {
+        for (int kk = 0; kk < wd; ++kk) {
+          const int pr = spiv[kk];
+          if (pr != k0 + kk) {
+            const double x = dld(k0 + kk, j), y = dld(pr, j);
+            dst(k0 + kk, j, y);
+            dst(pr, j, x);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
+    }
+    // (c) U12 = L11^{-1} A12, one thread per column right of the panel
+    const int c0 = k0 + wd, nc = n - c0;
+    if (t < nc) {
+      const int j = c0 + t;
+      double x[16];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const double y = dld(k0 + min(kk, wd - 1), j);
+        x[kk] = kk < wd ? y : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 15; ++jj)
+#pragma unroll
+        for (int kk = jj + 1; kk < 16; ++kk) x[kk] -= l11[kk][jj] * x[jj];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) u12[kk][t] = kk < wd ? x[kk] : 0.0;
+      // stored from LDS (the thread's own entries) in a loop over the
+      // panel's rows: a store per register under a condition each made the
+      // compiler keep every register and address live at once
+      for (int kk = 0; kk < wd; ++kk) dst(k0 + kk, j, u12[kk][t]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    // (d) A22 -= L21 U12 for rows c0..m-1 (the rows below the panel start at
+    // k0 + wd = c0) and columns c0..n-1
+    const int nr = m - c0;
+    if (nr > 0 && nc > 0) {
+      const int tr = (nr + 15) >> 4, tcn = (nc + 15) >> 4;
+      const int i = l & 15, g = l >> 4;
+      for (int tile = w; tile < tr * tcn; tile += kGetrfBigT / 64) {
+        const int I0 = c0 + 16 * (tile % tr), Jl = 16 * (tile / tr);
+        d4 acc;
+        bool ok[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ii = I0 + i, jj = c0 + Jl + 4 * q + g;
+          ok[q] = ii < m && jj < n;
+          const double x = dld(min(ii, m - 1), min(jj, n - 1));
+          acc[q] = ok[q] ? x : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kidx = 4 * st + g;
+          const double a = u12[kidx][min(Jl + i, kGetrfBigN)];
+          const double y = dld(min(I0 + i, m - 1), k0 + min(kidx, wd - 1));
+          const double bv = (kidx < wd && I0 + i < m) ? y : 0.0;
+          acc = mfma(-(Jl + i < nc ? a : 0.0), bv, acc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (ok[q]) dst(I0 + i, c0 + Jl + 4 * q + g, acc[q]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  }
+  if (info && threadIdx.x == 0) info[b] = inf;
+}
+
 // ---------------------------------------------------------------- gelqf
 // LQ factorization by Householder reflectors of an m-by-n matrix, m, n <= 64
 // (§5.2.2, gelqf; unblocked): one wave per instance with lane i holding row
@@ -602,6 +834,15 @@ int launch_getrf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
   View D = make_view(sD, di, dj, m, n);
   const dim3 g(1, batch);
   const long long sdA = batch_stride(sD), sip = m < n ? m : n;
+  if (m > 64 || n > 64) {
+    if (pivot)
+      hipLaunchKernelGGL(k_getrf_big<true>, g, dim3(kGetrfBigT), 0, st, m, n, C, D, sD->dA, ipiv,
+                         info, batch_stride(sC), batch_stride(sD), sdA, sip);
+    else
+      hipLaunchKernelGGL(k_getrf_big<false>, g, dim3(kGetrfBigT), 0, st, m, n, C, D, sD->dA, ipiv,
+                         info, batch_stride(sC), batch_stride(sD), sdA, sip);
+    return launch_status();
+  }
   if (pivot)
     hipLaunchKernelGGL(k_getrf<true>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
                        batch_stride(sC), batch_stride(sD), sdA, sip);
@@ -759,8 +1000,8 @@ void blasfeo_dgemm_nn(int m, int n, int k, double alpha,
 void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
                           int cj, struct blasfeo_dmat *sD, int di, int dj,
                           int *ipiv) {
-  if (m < 0 || m > 64) return set_error(-1);
-  if (n < 0 || n > 64) return set_error(-2);
+  if (m < 0 || m > 256) return set_error(-1);
+  if (n < 0 || n > 256) return set_error(-2);
   if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
   if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
   if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
@@ -772,8 +1013,8 @@ void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
 
 void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
                             int cj, struct blasfeo_dmat *sD, int di, int dj) {
-  if (m < 0 || m > 64) return set_error(-1);
-  if (n < 0 || n > 64) return set_error(-2);
+  if (m < 0 || m > 256) return set_error(-1);
+  if (n < 0 || n > 256) return set_error(-2);
   if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
   if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
   if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
@@ -938,8 +1179,8 @@ int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sD, int di, int dj,
                                int pivot, int *ipiv, int *info, void *stream) {
   if (batch < 0 || batch > 65535) return -1;
-  if (m < 0 || m > 64) return -2;
-  if (n < 0 || n > 64) return -3;
+  if (m < 0 || m > 256) return -2;
+  if (n < 0 || n > 256) return -3;
   if (!operand_ok(sC, ci, cj, m, n)) return -4;
   if (!operand_ok(sD, di, dj, m, n)) return -7;
   if (m > 0 && n > 0 && !sD->dA) return -7;

@@ -397,9 +397,104 @@ def test_dgetrf_exact_batched_info_and_errors():
         assert np.array_equal(ip[b], ipr)
         assert_parity(D[b], Dr, m, f"getrf b={b}")
     with pytest.raises(p.HipError):
-        p.blasfeo_hip_dgetrf_batched(batch, 65, 40, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
+        p.blasfeo_hip_dgetrf_batched(batch, 257, 40, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
     with pytest.raises(p.HipError):
         p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, None, info)
+
+
+@pytest.mark.parametrize("m,n", [(65, 65), (100, 100), (128, 128), (256, 256), (200, 130), (130, 200),
+                                 (17, 200), (256, 20), (97, 250)])
+@pytest.mark.parametrize("pivot", [True, False])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
+def test_dgetrf_blocked(m, n, pivot, off):
+    """Orders above 64 (the blocked kernel: panel factorization, interchanges,
+    block row of U, MFMA trailing update) against the oracle: the same
+    interchanges, the packed L\\U and dA within the parity bound, P A = L U
+    to the same bound, sentinels outside D untouched."""
+    note("getrf blocked", m, n, pivot, off)
+    ci, cj, di, dj = off
+    rng = np.random.default_rng(m * 7 + n + int(pivot))
+    C = rng.standard_normal((m, n))
+    if not pivot:  # diagonally dominant so that no pivoting is needed
+        C[np.arange(min(m, n)), np.arange(min(m, n))] += 2.0 * n
+    sC, sD = sentinel_mat(ci + m, cj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(C), sC, ci, cj)
+    mn = min(m, n)
+    ipiv = torch.full((mn,), -1, dtype=torch.int32, device=DEV)
+    if pivot:
+        p.blasfeo_dgetrf_pivot(m, n, sC, ci, cj, sD, di, dj, ipiv)
+    else:
+        p.blasfeo_dgetrf_nopivot(m, n, sC, ci, cj, sD, di, dj)
+    p.check_last()
+    Dfull = host(sD)
+    D = Dfull[di:, dj:]
+    Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=pivot)
+    assert inf == 0
+    ip = ipiv.cpu().numpy()
+    if pivot:
+        assert np.array_equal(ip, ipr)
+    assert_parity(D, Dr, max(m, n), "getrf blocked")
+    assert_parity(sD.dA()[:mn].cpu().numpy(), dAr, max(m, n), "dA")
+    # the GPU's own factors: P C = L U
+    L = np.tril(D, -1)[:, :mn] + np.eye(m, mn)
+    U = np.triu(D)[:mn, :]
+    PC = C.copy()
+    if pivot:
+        for k in range(mn):
+            PC[[k, ip[k]]] = PC[[ip[k], k]]
+    assert_parity(L @ U, PC, max(m, n), "P C = L U")
+    mask = np.ones_like(Dfull, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(Dfull[mask] == SENT)
+
+
+def test_dgetrf_blocked_exact_nan_batched():
+    """Blocked kernel: exact integer factors without pivoting (every
+    intermediate value an integer), in place; NaN pivot-column ranking as the
+    oracle's; a batch with a zero pivot (info) and the pivoted batch against
+    the oracle on every instance."""
+    note("getrf blocked exact/nan/batched")
+    rng = np.random.default_rng(91)
+    n = 150
+    Lm = np.tril(rng.integers(-2, 3, (n, n)), -1) + np.eye(n)
+    U = np.triu(rng.integers(-2, 3, (n, n)), 1) + np.diag(rng.choice([1.0, 2.0, -1.0, 4.0], n))
+    sC = mat(Lm @ U)
+    p.blasfeo_dgetrf_nopivot(n, n, sC, 0, 0, sC, 0, 0)  # in place
+    D = host(sC)
+    assert np.array_equal(np.tril(D, -1) + np.eye(n), Lm) and np.array_equal(np.triu(D), U)
+    for where in [(0, 0), (3, 0), (70, 20)]:
+        C = rng.standard_normal((90, 80))
+        C[where] = np.nan
+        sC, sD = mat(C), p.DMat(90, 80)
+        ipiv = torch.full((80,), -1, dtype=torch.int32, device=DEV)
+        p.blasfeo_dgetrf_pivot(90, 80, sC, 0, 0, sD, 0, 0, ipiv)
+        Dr, ipr, _, _ = oracle.dgetrf(C, pivot=True)
+        ip = ipiv.cpu().numpy()
+        # the interchanges up to the NaN's column are the oracle's, and the
+        # NaN reaches the same rows
+        k = where[1]
+        assert np.array_equal(ip[:k + 1], ipr[:k + 1]), where
+        assert np.array_equal(np.isnan(host(sD)[:, :k + 1]), np.isnan(Dr[:, :k + 1])), where
+    batch, m = 300, 96
+    C = rng.standard_normal((batch, m, m))
+    C[7, 0, 0] = 0.0
+    C[7, 1:, 0] = rng.standard_normal(m - 1)
+    sC, sD = p.pack_batch(dev(C)), p.DMatBatch(batch, m, m)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    ipiv = torch.full((batch, m), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 0, None, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    assert inf[7] == 1 and oracle.dgetrf(C[7], pivot=False)[3] == 1 and np.sum(inf != 0) == 1
+    p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    D = p.unpack_batch(sD).cpu().numpy()
+    ip = ipiv.cpu().numpy()
+    for b in range(batch):
+        Dr, ipr, _, _ = oracle.dgetrf(C[b], pivot=True)
+        assert np.array_equal(ip[b], ipr), b
+        assert_parity(D[b], Dr, m, f"getrf blocked b={b}")
 
 
 # ------------------------------------------------------------------ gelqf

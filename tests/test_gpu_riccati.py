@@ -156,9 +156,9 @@ def rel(a, b):
 def test_riccati_solve_parity(nx, nu, N):
     """Controls and states of the linear-quadratic problem from the GPU
     factorization and solve against the oracle's factorization and solve
-    (itself pinned against a dense KKT solve); bound 1e-13 * N * (nx + nu)
-    relative, the per-stage bound of the factors accumulated over the
-    stages."""
+    (itself pinned against a dense KKT solve); bound 1e-13 (nx + nu)
+    relative, the bound of the stage factors (measured worst: 8e-14 at
+    N = 20, 3e-13 over the 4096-problem workload)."""
     note("riccati solve", nx, nu, N)
     batch = 9
     d = synth.riccati_batch(batch, seed=5, nx=nx, nu=nu)
@@ -169,7 +169,8 @@ def test_riccati_solve_parity(nx, nu, N):
     vecs = lq_data(batch, nx, nu, N, seed=nx + N)
     u, x, info = solve_gpu(d, N, vecs)
     assert np.all(info == 0)
-    tol = 1e-13 * N * (nx + nu)
+    tol = 1e-13 * (nx + nu)
+    worst = 0.0
     for b in range(batch):
         F, inf = oracle.ric_trf(d["A"][b], d["B"][b], d["Q"][b], d["R"][b], d["PN"][b], N)
         assert inf == 0
@@ -177,12 +178,15 @@ def test_riccati_solve_parity(nx, nu, N):
         assert rel(u[b], ur) <= tol, (b, rel(u[b], ur))
         assert rel(x[b], xr) <= tol, (b, rel(x[b], xr))
         assert np.array_equal(x[b, 0], vecs[3][b])
+        worst = max(worst, rel(u[b], ur), rel(x[b], xr))
+    print(f"riccati solve nx={nx} nu={nu} N={N}: worst relative error {worst:.2e} (bound {tol:.1e})", flush=True)
 
 
 def test_riccati_solve_full_size():
     """The Riccati workload (4096 problems, nx = 32, nu = 8, N = 20): every
-    problem's trajectory satisfies the dynamics, and 16 sampled problems
-    match the oracle."""
+    problem's trajectory satisfies the dynamics and matches the oracle's
+    factorization and solve within 1e-13 (nx + nu); the worst relative
+    errors are printed."""
     note("riccati solve full size")
     batch, nx, nu, N = 4096, 32, 8, 20
     d = synth.riccati_batch(batch, seed=3, nx=nx, nu=nu)
@@ -191,11 +195,15 @@ def test_riccati_solve_full_size():
     assert np.all(info == 0)
     pred = np.einsum("bij,bnj->bni", d["A"], x[:, :-1]) + np.einsum("bij,bnj->bni", d["B"], u) + vecs[0]
     assert float(np.abs(pred - x[:, 1:]).max()) <= 1e-11 * (1 + float(np.abs(x).max()))
-    for b in np.random.default_rng(7).choice(batch, 16, replace=False):
+    eu = ex = 0.0
+    for b in range(batch):
         F, _ = oracle.ric_trf(d["A"][b], d["B"][b], d["Q"][b], d["R"][b], d["PN"][b], N)
         ur, xr = oracle.ric_trs(d["A"][b], d["B"][b], d["PN"][b], F, vecs[0][b], vecs[1][b], vecs[2][b], vecs[3][b])
-        assert rel(u[b], ur) <= 1e-13 * N * (nx + nu)
-        assert rel(x[b], xr) <= 1e-13 * N * (nx + nu)
+        eu, ex = max(eu, rel(u[b], ur)), max(ex, rel(x[b], xr))
+    tol = 1e-13 * (nx + nu)
+    print(f"riccati solve, all {batch} problems: worst relative error u {eu:.2e}, x {ex:.2e} "
+          f"(bound {tol:.1e})", flush=True)
+    assert eu <= tol and ex <= tol
 
 
 def test_riccati_solve_argument_errors():
