@@ -541,6 +541,9 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
   __shared__ double wkey[2][4];
   __shared__ int wpos[2][4];
   __shared__ int spiv[16];
+  __shared__ int cont[kGetrfBigT];  // row contents while composing interchanges
+  __shared__ int pdst[32], psrc[32];
+  __shared__ int npair;
   const int w = wave_id();
   const int mn = min(m, n);
   // D through a buffer descriptor: a 32-bit byte offset per access (the
@@ -656,18 +659,45 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
-    // (b) the interchanges in the columns outside the panel
+    // (b) the interchanges in the columns outside the panel, composed into
+    // one permutation of the (at most 32) rows they touch: one thread lists
+    // (destination, source) pairs, then every column moves its values with
+    // all loads in flight at once
     if (PIVOT) {
-      const int j = t;
-      if (j < n && (j < k0 || j >= k0 + wd)) {
+      if (t == 0) {
         for (int kk = 0; kk < wd; ++kk) {
-          const int pr = spiv[kk];
-          if (pr != k0 + kk) {
-            const double x = dld(k0 + kk, j), y = dld(pr, j);
-            dst(k0 + kk, j, y);
-            dst(pr, j, x);
-          }
+          cont[k0 + kk] = k0 + kk;
+          cont[spiv[kk]] = spiv[kk];
         }
+        for (int kk = 0; kk < wd; ++kk) {
+          const int ra = k0 + kk, rb = spiv[kk];
+          const int x = cont[ra];
+          cont[ra] = cont[rb];
+          cont[rb] = x;
+        }
+        int np2 = 0;
+        for (int kk = 0; kk < wd; ++kk)
+          for (int h = 0; h < 2; ++h) {
+            const int rr = h == 0 ? k0 + kk : spiv[kk];
+            if (cont[rr] != rr) {
+              pdst[np2] = rr;
+              psrc[np2] = cont[rr];
+              ++np2;
+              cont[rr] = rr;  // listed
+            }
+          }
+        npair = np2;
+      }
+      __syncthreads();
+      const int j = t, np2 = npair;
+      if (np2 > 0 && j < n && (j < k0 || j >= k0 + wd)) {
+        // pairs past the last are the last again (the same value to the
+        // same place), so that every access is unconditional
+        double vals[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) vals[q] = dld(psrc[min(q, np2 - 1)], j);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) dst(pdst[min(q, np2 - 1)], j, vals[q]);
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __syncthreads();
@@ -699,30 +729,48 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
     // k0 + wd = c0) and columns c0..n-1
     const int nr = m - c0;
     if (nr > 0 && nc > 0) {
-      const int tr = (nr + 15) >> 4, tcn = (nc + 15) >> 4;
+      // work item: one 16-row block of A22 and four 16-column blocks; the
+      // row block's L21 fragments are loaded once, then all 16 accumulator
+      // loads are in flight together
+      const int tr = (nr + 15) >> 4, tcn = (nc + 15) >> 4, tg = (tcn + 3) >> 2;
       const int i = l & 15, g = l >> 4;
-      for (int tile = w; tile < tr * tcn; tile += kGetrfBigT / 64) {
-        const int I0 = c0 + 16 * (tile % tr), Jl = 16 * (tile / tr);
-        d4 acc;
-        bool ok[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int ii = I0 + i, jj = c0 + Jl + 4 * q + g;
-          ok[q] = ii < m && jj < n;
-          const double x = dld(min(ii, m - 1), min(jj, n - 1));
-          acc[q] = ok[q] ? x : 0.0;
-        }
+      for (int item = w; item < tr * tg; item += kGetrfBigT / 64) {
+        const int I0 = c0 + 16 * (item % tr), Jg = 64 * (item / tr);
+        const int ii = I0 + i;
+        double bv[4];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kidx = 4 * st + g;
-          const double a = u12[kidx][min(Jl + i, kGetrfBigN)];
-          const double y = dld(min(I0 + i, m - 1), k0 + min(kidx, wd - 1));
-          const double bv = (kidx < wd && I0 + i < m) ? y : 0.0;
-          acc = mfma(-(Jl + i < nc ? a : 0.0), bv, acc);
+          const double y = dld(min(ii, m - 1), k0 + min(kidx, wd - 1));
+          bv[st] = (kidx < wd && ii < m) ? y : 0.0;
         }
+        d4 acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (ok[q]) dst(I0 + i, c0 + Jl + 4 * q + g, acc[q]);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int jj = c0 + Jg + 16 * u + 4 * q + g;
+            const double x = dld(min(ii, m - 1), min(jj, n - 1));
+            acc[u][q] = (ii < m && jj < n) ? x : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jl = Jg + 16 * u + i;
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const double a = u12[4 * st + g][min(jl, kGetrfBigN)];
+            acc[u] = mfma(-(jl < nc ? a : 0.0), bv[st], acc[u]);
+          }
+        }
+        if (ii < m) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int jj = c0 + Jg + 16 * u + 4 * q + g;
+              if (jj < n) dst(ii, jj, acc[u][q]);
+            }
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
