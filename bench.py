@@ -340,11 +340,17 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
     _, t6 = time_events(lambda: p.blasfeo_hip_dgetrf_batched(1, nb, nb, sG, 0, 0, sLU, 0, 0, 1, ipb, infb, stream),
                         reps, 2, stream)
     m6 = float(np.median(t6))
-    del sG, sLU
+    sLQ = p.DMatBatch(bb, nb, nb)
+    _, t7 = time_events(lambda: p.blasfeo_hip_dgelqf_batched(bb, nb, nb, sG, 0, 0, sLQ, 0, 0, stream), reps, 1,
+                        stream)
+    m7 = float(np.median(t7))
+    del sG, sLU, sLQ
     return {"getrf_pivot_256_batch_ms": round(m5, 3),
             "getrf_pivot_256_batch_gflops": round(bb * (2.0 / 3.0) * nb ** 3 / m5 / 1e6, 1),
             "getrf_pivot_256_batch_config": f"{bb} x {nb}x{nb}, blocked (panels of 16, MFMA trailing update)",
             "getrf_pivot_256_single_us": round(m6 * 1e3, 1),
+            "gelqf_256_batch_ms": round(m7, 3),
+            "gelqf_256_batch_gflops": round(bb * (4.0 / 3.0) * nb ** 3 / m7 / 1e6, 1),
             "gelqf_64_batch_ms": round(m4, 4),
             "gelqf_64_batch_gflops": round(batch * (4.0 / 3.0) * nl ** 3 / m4 / 1e6, 1),
             "getrf_pivot_64_batch_ms": round(m3, 4),

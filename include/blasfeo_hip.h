@@ -201,13 +201,16 @@ void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,
 void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
                             int cj, struct blasfeo_dmat *sD, int di, int dj);
 
-/* gelqf (§5.2.2; unblocked): LQ factorization C = L Q of the m-by-n matrix
- * C (m, n <= 64) by Householder reflectors, in LAPACK's compact form: L on
+/* gelqf (§5.2.2): LQ factorization C = L Q of the m-by-n matrix C
+ * (m, n <= 256) by Householder reflectors, in LAPACK's compact form: L on
  * and below the diagonal of D, reflector k's vector to the right of the
  * diagonal of row k (its k-th entry 1 implicit), tau_k in sD->dA[k]
  * (min(m,n) entries); Q = H_{min-1} ... H_0 with H_k = I - tau_k v v'.
- * Errors: -1 m, -2 n (outside 0..64), -3 C, -6 D (or a NULL dA).  C and D
- * may be the same matrix at the same offsets. */
+ * m, n <= 64: unblocked, the oracle's operations in its order (identical
+ * bits); larger: blocked by panels of 16 rows, the rows below a panel
+ * updated as A2 -= ((A2 V^T) T) V on the matrix cores (the factors agree to
+ * rounding).  Errors: -1 m, -2 n (outside 0..256), -3 C, -6 D (or a NULL
+ * dA).  C and D may be the same matrix at the same offsets. */
 void blasfeo_dgelqf(int m, int n, struct blasfeo_dmat *sC, int ci, int cj,
                     struct blasfeo_dmat *sD, int di, int dj);
 
@@ -307,7 +310,8 @@ int blasfeo_hip_dgetrf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sD, int di, int dj,
                                int pivot, int *ipiv, int *info, void *stream);
 
-/* Uniform batch of gelqf (tau of instance b in its D's dA).  Returns 0,
+/* Uniform batch of gelqf (m, n <= 256 as above; tau of instance b in its
+ * D's dA).  Returns 0,
  * -i for bad argument i, or a HIP error code. */
 int blasfeo_hip_dgelqf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sC, int ci, int cj,

@@ -779,6 +779,218 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
   if (info && threadIdx.x == 0) info[b] = inf;
 }
 
+// ---------------------------------------------------------------- gelqf, blocked
+// LQ factorization (Householder reflectors, LAPACK's compact form) of an
+// m-by-n matrix with max(m, n) > 64 (up to 256), blocked by panels of 16
+// rows (§5.2.2: the paper's gelqf blocks its reflectors), one workgroup of
+// 256 threads per instance, D updated in place after a copy of C:
+//   (a) the panel's rows are held one column per thread (16 registers);
+//       each reflector's squared norm and each remaining row's product with
+//       it are workgroup sums (a shuffle tree per wave, then the four
+//       partial sums through LDS in a fixed order), and the reflector is
+//       applied to the panel's remaining rows;
+//   (b) the reflectors V (unit leading entry) go to LDS, their Gram matrix
+//       V V^T is formed on the f64 MFMA, and the upper triangular T with
+//       H_0 H_1 ... H_{w-1} = I - V^T T V by the forward recurrence
+//       T[0:k,k] = -tau_k T[0:k,0:k] (V V^T)[0:k,k], one lane per row of T;
+//   (c) every 16-row block below the panel: A2 -= ((A2 V^T) T) V, as
+//       W^T = V A2^T, Z^T = T^T W^T and A2 -= Z V on the MFMA.
+// The oracle's reflectors with the products in another order: the factors
+// agree to rounding.
+constexpr int kGelqfBigT = 256;  // threads per instance = the largest n
+constexpr int kGelqfBigN = 256;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+__global__ __launch_bounds__(kGelqfBigT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gelqf_big(int m, int n, View C, View D, double *tau, long long sC, long long sD,
+                 long long stau) {
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *taub = tau + b * stau;
+  __shared__ double vl[16][kGelqfBigN + 1];  // the panel's reflectors, columns r0..n-1
+  __shared__ double tt[16][17];              // T
+  __shared__ double gg[16][17];              // V V^T
+  __shared__ double red[2][16][4];           // [parity][sum][wave]
+  __shared__ double bc[2];                   // the diagonal entry alpha
+  __shared__ double stk[16];                 // the panel's tau
+  const int w = wave_id();
+  const int mn = min(m, n);
+  const brsrc rD = make_rsrc(D.p, 8LL * ((D.ai + m + 15) & ~15) * D.cn);
+  auto doff = [&](int i, int j) { return 8 * (int)pm_off(D.ai + i, D.aj + j, D.cn); };
+  auto dld = [&](int i, int j) { return bload(rD, doff(i, j), 0); };
+  auto dst = [&](int i, int j, double x) { bstore(rD, doff(i, j), 0, x); };
+  for (int e = threadIdx.x; e < m * n; e += kGelqfBigT) {
+    const int i = e % m, j = e / m;
+    dst(i, j, C.p[pm_off(C.ai + i, C.aj + j, C.cn)]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __syncthreads();
+  for (int r0 = 0; r0 < mn; r0 += 16) {
+    const int wd = min(16, mn - r0);
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));  // recomputed per panel, not kept live
+    const int l = t & 63;
+    const int j = t;  // this thread's column
+    const bool col = j >= r0 && j < n;
+    const int jc = min(max(j, r0), n - 1);
+    // (a) the panel's rows
+    double P[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double x = dld(r0 + min(kk, wd - 1), jc);
+      P[kk] = (col && kk < wd) ? x : 0.0;
+    }
+    for (int kk = 0; kk < wd; ++kk) {
+      const int k = r0 + kk;
+      const int par = kk & 1;
+      double pk = P[0];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) pk = kk == e ? P[e] : pk;
+      const double sw = wave_sum((col && j > k) ? pk * pk : 0.0);
+      if (l == 0) red[par][0][w] = sw;
+      if (j == k) bc[par] = pk;
+      __syncthreads();
+      const double ss = ((red[par][0][0] + red[par][0][1]) + red[par][0][2]) + red[par][0][3];
+      const double alpha = bc[par];
+      const double xn = sqrt(ss);
+      double tk = 0.0, sc = 1.0, beta = alpha;
+      if (xn != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tk = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      // the reflector (v_k = 1, zero left of k) and row k of the panel
+      const double v = j > k ? pk * sc : (j == k ? 1.0 : 0.0);
+      const double rowk = j > k ? v : (j == k ? beta : pk);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) P[e] = (kk == e && col) ? rowk : P[e];
+      if (t == 0) {
+        taub[k] = tk;
+        stk[kk] = tk;
+      }
+      if (tk != 0.0) {
+        // w_i = sum_{j >= k} P[i][j] v_j for the panel rows below k, then
+        // P[i][j] -= tau w_i v_j
+        double part[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[e] = (col && e > kk && e < wd && j >= k) ? P[e] * v : 0.0;
+#pragma unroll
+        for (int e = 1; e < 16; ++e) part[e] = wave_sum(part[e]);
+        if (l == 0) {
+#pragma unroll
+          for (int e = 1; e < 16; ++e) red[par][e][w] = part[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 1; e < 16; ++e) {
+          if (e > kk && e < wd) {
+            const double wi = tk * (((red[par][e][0] + red[par][e][1]) + red[par][e][2]) + red[par][e][3]);
+            P[e] = (col && j >= k) ? P[e] - wi * v : P[e];
+          }
+        }
+      }
+    }
+    // the panel's rows back to D; the reflectors to LDS
+    if (col) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = r0 + kk;
+        vl[kk][j - r0] = kk < wd ? (j > k ? P[kk] : (j == k ? 1.0 : 0.0)) : 0.0;
+      }
+      for (int kk = 0; kk < wd; ++kk) {
+        double x = P[0];
+#pragma unroll
+        for (int e = 1; e < 16; ++e) x = kk == e ? P[e] : x;
+        dst(r0 + kk, j, x);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    const int ncv = n - r0;  // columns of V
+    const int rb0 = r0 + wd, nrow = m - rb0;
+    if (nrow > 0) {
+      const int i = l & 15, g = l >> 4;
+      // (b) V V^T (wave 0), then T (lanes 0..15 of wave 0)
+      if (w == 0) {
+        d4 G = zero4();
+        for (int J = 0; J < ncv; J += 4) {
+          const int jj = J + g;
+          const double x = jj < ncv ? vl[i][min(jj, kGelqfBigN)] : 0.0;
+          G = mfma(x, x, G);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gg[g + 4 * r][i] = G[r];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (l < 16) {
+          const int a = l;
+          double trow[16];
+#pragma unroll
+          for (int kk = 0; kk < 16; ++kk) {
+            const double tk = kk < wd ? stk[kk] : 0.0;
+            double sm = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < kk; ++bb) sm = (bb >= a) ? sm + trow[bb] * gg[bb][kk] : sm;
+            trow[kk] = kk == a ? tk : (kk > a ? -tk * sm : 0.0);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 16; ++kk) tt[a][kk] = (a < wd && kk < wd) ? trow[kk] : 0.0;
+        }
+      }
+      __syncthreads();
+      // (c) A2 -= ((A2 V^T) T) V, one 16-row block per wave at a time
+      const int nrb = (nrow + 15) >> 4;
+      for (int rb = w; rb < nrb; rb += kGelqfBigT / 64) {
+        const int ii = rb0 + 16 * rb + i;
+        const int iic = min(ii, m - 1);
+        d4 Wt = zero4();  // W^T = V A2^T, T-tile [reflector][row]
+        for (int J = 0; J < ncv; J += 16) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int jj = J + 4 * s4 + g;
+            const double a = jj < ncv ? vl[i][min(jj, kGelqfBigN)] : 0.0;
+            const double y = dld(iic, r0 + min(jj, ncv - 1));
+            Wt = mfma(a, (ii < m && jj < ncv) ? y : 0.0, Wt);
+          }
+        }
+        d4 Zt = zero4();  // Z^T = T^T W^T
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Zt = mfma(tt[g + 4 * r][i], Wt[r], Zt);
+        for (int J = 0; J < ncv; J += 16) {
+          d4 acc;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int jj = J + 4 * s4 + g;
+            const double y = dld(iic, r0 + min(jj, ncv - 1));
+            acc[s4] = (ii < m && jj < ncv) ? y : 0.0;
+          }
+          const int jv = J + i;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double vt = jv < ncv ? vl[g + 4 * r][min(jv, kGelqfBigN)] : 0.0;
+            acc = mfma(-vt, Zt[r], acc);
+          }
+          if (ii < m) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const int jj = J + 4 * s4 + g;
+              if (jj < ncv) dst(ii, r0 + jj, acc[s4]);
+            }
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- gelqf
 // LQ factorization by Householder reflectors of an m-by-n matrix, m, n <= 64
 // (§5.2.2, gelqf; unblocked): one wave per instance with lane i holding row
@@ -865,8 +1077,12 @@ int launch_gelqf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
   if (batch == 0 || m == 0 || n == 0) return 0;
   View C = make_view(sC, ci, cj, m, n);
   View D = make_view(sD, di, dj, m, n);
-  hipLaunchKernelGGL(k_gelqf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
-                     batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  if (m > 64 || n > 64)
+    hipLaunchKernelGGL(k_gelqf_big, dim3(1, batch), dim3(kGelqfBigT), 0, st, m, n, C, D, sD->dA,
+                       batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  else
+    hipLaunchKernelGGL(k_gelqf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
+                       batch_stride(sC), batch_stride(sD), batch_stride(sD));
   return launch_status();
 }
 
@@ -1073,8 +1289,8 @@ void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
 
 void blasfeo_dgelqf(int m, int n, struct blasfeo_dmat *sC, int ci, int cj,
                     struct blasfeo_dmat *sD, int di, int dj) {
-  if (m < 0 || m > 64) return set_error(-1);
-  if (n < 0 || n > 64) return set_error(-2);
+  if (m < 0 || m > 256) return set_error(-1);
+  if (n < 0 || n > 256) return set_error(-2);
   if (!operand_ok(sC, ci, cj, m, n)) return set_error(-3);
   if (!operand_ok(sD, di, dj, m, n)) return set_error(-6);
   if (m > 0 && n > 0 && !sD->dA) return set_error(-6);
@@ -1243,8 +1459,8 @@ int blasfeo_hip_dgelqf_batched(int batch, int m, int n,
                                const struct blasfeo_dmat *sD, int di, int dj,
                                void *stream) {
   if (batch < 0 || batch > 65535) return -1;
-  if (m < 0 || m > 64) return -2;
-  if (n < 0 || n > 64) return -3;
+  if (m < 0 || m > 256) return -2;
+  if (n < 0 || n > 256) return -3;
   if (!operand_ok(sC, ci, cj, m, n)) return -4;
   if (!operand_ok(sD, di, dj, m, n)) return -7;
   if (m > 0 && n > 0 && !sD->dA) return -7;

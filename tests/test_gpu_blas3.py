@@ -544,7 +544,57 @@ def test_dgelqf_batched_and_zero_row():
         assert_parity(D[b], Dr, n, f"gelqf b={b}")
         assert_parity(tau[b], taur, n, f"tau b={b}")
     with pytest.raises(p.HipError):
-        p.blasfeo_hip_dgelqf_batched(batch, 65, n, sC, 0, 0, sD, 0, 0)
+        p.blasfeo_hip_dgelqf_batched(batch, 257, n, sC, 0, 0, sD, 0, 0)
+
+
+@pytest.mark.parametrize("m,n", [(65, 65), (100, 100), (128, 128), (256, 256), (200, 130), (130, 200),
+                                 (17, 200), (256, 20), (97, 250)])
+@pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
+def test_dgelqf_blocked(m, n, off):
+    """Orders above 64 (the blocked kernel: panel reflectors, T from the
+    reflectors' Gram matrix, MFMA block update of the rows below) against
+    the oracle: reflectors, L and tau within the parity bound; the GPU's own
+    factors reproduce A; sentinels outside D untouched."""
+    note("gelqf blocked", m, n, off)
+    ci, cj, di, dj = off
+    A = np.random.default_rng(m * 11 + n).standard_normal((m, n))
+    sC, sD = sentinel_mat(ci + m, cj + n), sentinel_mat(di + m, dj + n)
+    p.pack(dev(A), sC, ci, cj)
+    p.blasfeo_dgelqf(m, n, sC, ci, cj, sD, di, dj)
+    p.check_last()
+    Dfull = host(sD)
+    D = Dfull[di:, dj:]
+    k = min(m, n)
+    tau = sD.dA()[:k].cpu().numpy()
+    Dr, taur = oracle.dgelqf(A)
+    assert_parity(D, Dr, max(m, n), "gelqf blocked")
+    assert_parity(tau, taur, max(m, n), "tau")
+    Q = oracle.lq_q(D, tau)
+    assert np.abs(np.tril(D)[:, :k] @ Q[:k] - A).max() <= 1e-13 * max(m, n)
+    mask = np.ones_like(Dfull, dtype=bool)
+    mask[di:, dj:] = False
+    assert np.all(Dfull[mask] == SENT)
+
+
+def test_dgelqf_blocked_batched_zero_row_in_place():
+    """Blocked kernel: a batch with an identity reflector (a zero row right
+    of the diagonal), every instance against the oracle; in place."""
+    note("gelqf blocked batched")
+    rng = np.random.default_rng(92)
+    batch, m, n = 200, 90, 120
+    A = rng.standard_normal((batch, m, n))
+    A[5, 0, 1:] = 0.0
+    A[6, 40, 41:] = 0.0
+    sC = p.pack_batch(dev(A))
+    p.blasfeo_hip_dgelqf_batched(batch, m, n, sC, 0, 0, sC, 0, 0)
+    torch.cuda.synchronize()
+    D = p.unpack_batch(sC).cpu().numpy()
+    tau = sC.dA()[:, :m].cpu().numpy()
+    assert tau[5, 0] == 0.0
+    for b in range(batch):
+        Dr, taur = oracle.dgelqf(A[b])
+        assert_parity(D[b], Dr, n, f"gelqf blocked b={b}")
+        assert_parity(tau[b], taur, n, f"tau b={b}")
 
 
 # ------------------------------------------------------------------ potrf_l_mn (stacking)
