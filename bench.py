@@ -29,13 +29,18 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_sha():
-    """Hash of the sources of the timed kernel (the counter-based traffic in
-    profiles/ is used only while it still matches)."""
+    """Hash of the code of the timed kernel's sources, comments and white
+    space removed (the counter-based traffic in profiles/ is used only while
+    it still matches, so any change to the code invalidates it)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("fused.hip", "blocks.hpp", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_1704_02457_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1704_02457_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

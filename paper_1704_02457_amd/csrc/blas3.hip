@@ -3,7 +3,7 @@
 // arbitrary sub-matrices (any (ai, aj), any
 // sizes), single instance or uniform batch (one batch index per grid row).
 //
-// These are the "generic" kernel variant of §4.4.2: every 16x16 block is
+// These are the generic kernel variant of §4.4.2: every 16x16 block is
 // computed as a full register tile and stored through a masked store that
 // also handles sub-matrices not aligned to a panel top.  Operands are read
 // straight from the caller's panel-major buffers; nothing is repacked (§4.3).

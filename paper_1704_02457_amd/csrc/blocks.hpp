@@ -262,7 +262,8 @@ __device__ __forceinline__ void store_tileT(const View &v, int i0, int j0,
 
 // ---------------------------------------------------------------------------
 // Register-resident 16x16 Cholesky and triangular inversion (§4.6: the
-// "unblocked" LAPACK part is a subroutine on a register-resident block).
+// unblocked part of the LAPACK-style routines is a subroutine that works on a
+// block held in registers).
 // ---------------------------------------------------------------------------
 
 // V = U^{-1} for an upper triangular T-tile U with inv[k] = 1/U[k][k]
