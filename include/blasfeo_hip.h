@@ -589,7 +589,10 @@ int blasfeo_hip_dposv_vbatched_noalloc(const blasfeo_hip_plan *plan,
                                        void *X, int *info, void *stream);
 /* Records the class launches of an execution with these pointers into a
  * hipGraph and instantiates it (replaces any earlier graph of the plan).
- * A set-up call: it launches nothing. */
+ * The size classes touch disjoint instances and become parallel branches of
+ * the graph (forked from and joined to the capturing stream through
+ * streams and events the plan created), so that one class's last
+ * workgroups overlap the others'.  A set-up call: it launches nothing. */
 int blasfeo_hip_plan_capture(blasfeo_hip_plan *plan, const void *A, void *L,
                              const void *B, void *X, int *info, void *work);
 /* Picks the launch configuration of every size class (the tile and panel

@@ -31,6 +31,12 @@ struct blasfeo_hip_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
+  // captured graphs run the size classes as parallel branches: one stream
+  // per class forked from and joined to the capturing stream by events
+  static constexpr int kMaxAux = 8;
+  hipStream_t aux[kMaxAux] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kMaxAux] = {};
   // Workspace of an FP64 execution: for the instances with n > 64, the
   // inverses W_j of the diagonal blocks (256 doubles per 16-row block), kept
   // for the back substitution, at W + wwoff[id] doubles.

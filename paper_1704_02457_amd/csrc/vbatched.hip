@@ -819,6 +819,11 @@ int blasfeo_hip_dposv_vbatched_plan(int batch, const int *n_host, int nrhs,
     if (e == hipSuccess) e = hipMemcpy(p->d_ids, ids.data(), batch * sizeof(int), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  for (int i = 0; i < (int)p->buckets.size() && i < blasfeo_hip_plan::kMaxAux && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming);
+  }
   int nbm = 0;
   for (const auto &bk : p->buckets)
     if (bk.kind == 0) nbm = std::max(nbm, bk.nbmax);
@@ -920,8 +925,26 @@ int blasfeo_hip_plan_capture(blasfeo_hip_plan *p, const void *A, void *L,
   drop_graph(p);
   hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return (int)e;
-  const int le = launch_all(p, (const double *)A, (double *)L, (const double *)B,
-                            (double *)X, info, (double *)work, p->cap);
+  // the classes touch disjoint instances (and disjoint parts of the
+  // workspace): each becomes its own branch of the graph, so that one
+  // class's last workgroups overlap the others' instead of each launch
+  // draining the GPU before the next starts; the n > 64 classes first
+  int le = (int)hipEventRecord(p->ev_fork, p->cap);
+  int nbr = 0;
+  for (int pass = 0; pass < 2 && !le; ++pass)
+    for (const auto &bk : p->buckets) {
+      if ((pass == 0) != (bk.kind == 0) || bk.count == 0 || le) continue;
+      hipStream_t s = nbr < blasfeo_hip_plan::kMaxAux && p->aux[nbr] ? p->aux[nbr] : p->cap;
+      if (s != p->cap) le = (int)hipStreamWaitEvent(s, p->ev_fork, 0);
+      if (!le)
+        le = launch_bucket(p, bk, (const double *)A, (double *)L, (const double *)B,
+                           (double *)X, info, (double *)work, s);
+      if (!le && s != p->cap) {
+        le = (int)hipEventRecord(p->ev_join[nbr], s);
+        if (!le) le = (int)hipStreamWaitEvent(p->cap, p->ev_join[nbr], 0);
+      }
+      ++nbr;
+    }
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(p->cap, &g);
   if (le) {
@@ -1100,6 +1123,11 @@ void blasfeo_hip_plan_destroy(blasfeo_hip_plan *p) {
   if (p->d_voff) (void)hipFree(p->d_voff);
   if (p->d_ids) (void)hipFree(p->d_ids);
   if (p->cap) (void)hipStreamDestroy(p->cap);
+  for (int i = 0; i < blasfeo_hip_plan::kMaxAux; ++i) {
+    if (p->aux[i]) (void)hipStreamDestroy(p->aux[i]);
+    if (p->ev_join[i]) (void)hipEventDestroy(p->ev_join[i]);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->d_woff) (void)hipFree(p->d_woff);
   if (p->d_mx_ids) (void)hipFree(p->d_mx_ids);
   if (p->d_wwoff) (void)hipFree(p->d_wwoff);
