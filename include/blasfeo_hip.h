@@ -189,10 +189,14 @@ void blasfeo_dpotrf_l_mn(int m, int n, struct blasfeo_dmat *sC, int ci,
  * row ipiv[k] >= k (0-based, the first row of largest magnitude in column
  * k) before step k; ipiv is a device array of min(m,n) ints.  A zero pivot
  * does not stop the factorization (as in LAPACK; the batched entry point
- * reports it in info).  m, n <= 64: unblocked, the oracle's operations in
+ * reports it in info).  m, n <= 32: unblocked, the oracle's operations in
  * its order (identical bits); larger: blocked by panels of 16 columns with
- * the trailing update on the matrix cores (§5.2.2's blocked form; the
- * factors agree to rounding).  Errors: -1 m, -2 n (outside 0..256), -3 C,
+ * the trailing update on the matrix cores (§5.2.2's blocked form; one wave
+ * per instance with the matrix in registers up to 64, a workgroup per
+ * instance above), the factors agreeing to rounding and the interchanges
+ * wherever the pivot candidates differ by more than the rounding (the
+ * reciprocal of a pivot is the hardware estimate refined by Newton steps,
+ * within an ulp).  Errors: -1 m, -2 n (outside 0..256), -3 C,
  * -6 D (or a NULL dA), -9 a NULL ipiv.  C and D may be the same matrix at
  * the same offsets. */
 void blasfeo_dgetrf_pivot(int m, int n, struct blasfeo_dmat *sC, int ci,

@@ -499,6 +499,361 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   if (info && l == 0) info[b] = inf;
 }
 
+// ---------------------------------------------------------------- getrf, one wave, MFMA
+// LU of an m-by-n matrix with 32 < max(m, n) <= 64, blocked by panels of 16
+// columns as in §5.2.2 (getrf), one wave per instance with the whole matrix
+// in registers as 16 T-tiles (register r of lane (c, g) of tile (t, J) holds
+// A[16t + g + 4r][16J + c]).  Rows are never moved: row i keeps its
+// registers, pos(i) is its current position, and the rows are stored to
+// their final positions at the end.  Per panel of columns k0..k0+15:
+//   (a) the panel's column tile goes through LDS to one row per lane (16
+//       registers) and the oracle's unblocked sweep runs over it: the pivot
+//       is the row of largest magnitude among positions >= k (a wave max on
+//       DPP, ties to the smallest position), the pivot row's entries reach
+//       the other lanes by readlane, and each row below forms its
+//       multiplier and updates the panel's remaining columns;
+//   (b) the pivot rows' entries right of the panel (A12, written to LDS by
+//       the lanes holding them) give U12 = L11^{-1} A12 by forward
+//       substitution, one lane per column;
+//   (c) every row below the panel's pivot rows: A[i, right] -= L[i, panel]
+//       U12 on the f64 MFMA (L[i, j] the multiplier of row i at step j); the
+//       pivot rows take their rows of U12, and rows finished by earlier
+//       panels keep their values.
+// The oracle's operations with the updates right of a panel delayed to (c)
+// and fused multiply-adds: the factors agree to rounding, the interchanges
+// wherever the pivot candidates differ by more than the rounding, and on
+// data whose every intermediate value is exact the results are the oracle's
+// bit for bit.
+// One step of a wave max of non-negative, non-NaN doubles: lanes without a
+// source lane read 0 (bound_ctrl), which never exceeds the maximum.  The max
+// is a single v_max_f64 (the operands are never signalling NaNs, so the
+// quieting that fmax adds is not needed).
+template <int CTRL>
+__device__ __forceinline__ double dpp_max_step(double x) {
+  const long long xb = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)xb, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(xb >> 32), CTRL, 0xf, 0xf, true);
+  const double y = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ int dpp_min_step(int x) {
+  return min(x, __builtin_amdgcn_update_dpp(0x7fffffff, x, CTRL, RM, 0xf, false));
+}
+
+// A byte offset past the end of every descriptor the kernel below builds (a
+// descriptor covers one instance's matrix, far below 2 GiB): buffer loads at
+// it read zero.
+constexpr int kOobOffset = 0x7ffffff0;
+
+template <bool PIVOT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_getrf_mf(
+    int m, int n, View C, View D, double *dA, int *ipiv, int *info, long long sC, long long sD,
+    long long sdA, long long sip) {
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *dAb = dA ? dA + b * sdA : nullptr;
+  int *ipb = ipiv ? ipiv + b * sip : nullptr;
+  __shared__ double sp[64][17];  // one column tile, a row per line
+  __shared__ double su[20][49];  // A12 of the panel's pivot rows, then U12 (rows 16..19: discarded writes)
+  __shared__ __align__(16) double slT[16][16];  // L11 transposed (below its diagonal)
+  __shared__ int spos[64];       // position of each row (-1 beyond m)
+  __shared__ int sipv[64];       // ipiv and dA, stored at the end
+  __shared__ double sdav[64];
+  __shared__ double szero;       // a zero that masked reads read (the select
+                                 // is on the address, so no read waits under a branch)
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;
+  const int mn = min(m, n);
+  const int tr = (m + 15) >> 4, tc = (n + 15) >> 4;
+  const brsrc rC = make_rsrc(C.p, 8LL * ((C.ai + m + 15) & ~15) * C.cn);
+  const brsrc rD = make_rsrc(D.p, 8LL * ((D.ai + m + 15) & ~15) * D.cn);
+  // The loads go out column tile by column tile, the first panel's first,
+  // so that its sweep starts while the others are in flight; an element
+  // outside the matrix is read at an offset past the end of the buffer,
+  // which reads as zero (no select waiting on the load).
+  d4 A[4][4];
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * t + g + 4 * r, j = 16 * J + c;
+        const int off = (i < m && j < n) ? 8 * (int)pm_off(C.ai + i, C.aj + j, C.cn) : kOobOffset;
+        A[t][J][r] = bload(rC, off, 0);
+      }
+  __builtin_amdgcn_s_waitcnt(0);
+  const bool live = l < m;
+  int pos = l;
+  int inf = 0;
+  if (l == 0) szero = 0.0;
+  // The panel loop runs as a loop (its body once in the code, which keeps
+  // the kernel within the instruction cache): the current panel's column
+  // tile is always A[.][0], the trailing ones A[.][1..ntr], and the tile
+  // columns rotate by one at the end of each panel, by four in all.
+  const int np = (mn + 15) >> 4;
+#pragma unroll 1
+  for (int p = 0; p < np; ++p) {
+    const int k0 = 16 * p;
+    const int wd = min(16, mn - k0);
+    const int ntr = tc - 1 - p;  // trailing column tiles
+    // (a) the panel, one row per lane
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sp[16 * t + g + 4 * r][c] = A[t][0][r];
+    wave_sync();
+    double pr[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) pr[j] = sp[l][j];
+    wave_sync();
+    int ipv = 0;  // step l's pivot position and reciprocal
+    double dav = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      if (kk >= wd) continue;
+      const int k = k0 + kk;
+      const double v = pr[kk];
+      int pl = k, ppos = k;
+      if (PIVOT) {
+        // the oracle's scan keeps position k unless a later row is strictly
+        // larger: a NaN there wins and a NaN elsewhere never does (keys:
+        // |v| for the candidates, +inf for a NaN at position k, below zero
+        // for a NaN elsewhere and for the other rows).  The wave max runs on
+        // the keys rounded to binary32 (a rounding that keeps their order,
+        // ties aside): a single lane at the maximum is the pivot; several
+        // are resolved by their binary64 keys, then by position.
+        const double av = __builtin_isnan(v) ? (pos == k ? __builtin_inf() : -0.5) : fabs(v);
+        const bool cand = live && pos >= k;
+        const float kf = cand ? (float)av : -1.0f;
+        float x = kf;
+        asm volatile(
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+            "s_nop 1"
+            : "+v"(x));
+        const float mxf = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+        unsigned long long hit = __ballot(cand && kf == mxf);
+        if (hit & (hit - 1)) {
+          const bool h = (hit >> l) & 1;
+          double y = h ? av : -1.0;
+          y = dpp_max_step<0x111>(y);
+          y = dpp_max_step<0x112>(y);
+          y = dpp_max_step<0x114>(y);
+          y = dpp_max_step<0x118>(y);
+          y = dpp_max_step<0x142>(y);
+          y = dpp_max_step<0x143>(y);
+          const double mx = readlane_d(y, 63);
+          hit = __ballot(h && av == mx);
+        }
+        pl = __builtin_ctzll(hit);
+        if (hit & (hit - 1)) {
+          int q = (hit >> l) & 1 ? pos : 0x7fffffff;
+          q = dpp_min_step<0x111, 0xf>(q);
+          q = dpp_min_step<0x112, 0xf>(q);
+          q = dpp_min_step<0x114, 0xf>(q);
+          q = dpp_min_step<0x118, 0xf>(q);
+          q = dpp_min_step<0x142, 0xa>(q);
+          q = dpp_min_step<0x143, 0xc>(q);
+          const int best = __builtin_amdgcn_readlane(q, 63);
+          pl = __builtin_ctzll(__ballot(live && pos == best));
+        }
+        ppos = __builtin_amdgcn_readlane(pos, pl);
+        if (pos == k) pos = ppos;
+        if (l == pl) pos = k;
+      }
+      const double piv = readlane_d(v, pl);
+      if (piv == 0.0 && inf == 0) inf = k + 1;
+      // 1/piv: the hardware reciprocal and two Newton steps (within an ulp)
+      // for pivots of moderate magnitude, the division otherwise (zero,
+      // infinite, NaN or extreme pivots keep the oracle's special values)
+      double invp;
+      const double ap = fabs(piv);
+      if (ap > 0x1p-1000 && ap < 0x1p1000) {
+        double r = __builtin_amdgcn_rcp(piv);
+        r = fma(r, fma(-piv, r, 1.0), r);
+        invp = fma(r, fma(-piv, r, 1.0), r);
+      } else {
+        invp = 1.0 / piv;
+      }
+      if (l == kk) {
+        ipv = ppos;
+        dav = invp;
+      }
+      double pc[16];
+#pragma unroll
+      for (int j = kk + 1; j < 16; ++j) pc[j] = readlane_d(pr[j], pl);
+      if (live && pos > k) {
+        const double mult = v * invp;
+        pr[kk] = mult;
+#pragma unroll
+        for (int j = kk + 1; j < 16; ++j) pr[j] = fma(-mult, pc[j], pr[j]);
+      }
+    }
+    if (l < wd) {
+      sipv[k0 + l] = ipv;
+      sdav[k0 + l] = dav;
+    }
+    // the panel back into its column tile; the multipliers (transposed, for
+    // the MFMA's left operand), the pivot rows and the positions to LDS
+    spos[l] = live ? pos : -1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sp[l][j] = pr[j];
+    const int kp = pos - k0;
+    if (live && kp >= 0 && kp < wd) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) slT[j][kp] = pr[j];
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A[t][0][r] = sp[16 * t + g + 4 * r][c];
+    d4 X[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ps = spos[16 * t + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = g + 4 * r;
+        X[t][r] = *((j < wd && ps >= k0 + wd) ? &sp[16 * t + c][j] : &szero);
+      }
+    }
+    wave_sync();
+    if (ntr > 0) {
+    // (b) A12 of the pivot rows: each lane writes the entries of its rows,
+    // a pivot row's to its row of su and the others' to a row past the
+    // sixteenth (unconditional stores, distinct addresses per lane)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= tr) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = spos[16 * t + g + 4 * r] - k0;
+        const int qd = (q >= 0 && q < wd) ? q : 16 + g;
+#pragma unroll
+        for (int J = 1; J < 4; ++J)
+          if (J <= ntr) su[qd][16 * (J - 1) + c] = A[t][J][r];
+      }
+    }
+    wave_sync();
+    // U12 = L11^{-1} A12 by columns of L11 (rows wd..15 of the result zero)
+    if (l < 16 * ntr) {
+      double x[16];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) x[kk] = su[kk][l];
+#pragma unroll
+      for (int j = 0; j < 15; ++j) {
+        const double xj = x[j];
+#pragma unroll
+        for (int kk = j + 1; kk < 16; ++kk) x[kk] = fma(-slT[j][kk], xj, x[kk]);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) su[kk][l] = kk < wd ? x[kk] : 0.0;
+    }
+    wave_sync();
+    // (c) the trailing update of the rows below the panel's pivot rows
+    // (their rows of X are the multipliers, every other row's zero: with a
+    // finite U12 the product leaves those rows as they are, up to the sign
+    // of a zero; otherwise their values are kept by a select)
+    d4 Y[4];
+    bool fin = true;
+#pragma unroll
+    for (int J = 1; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Y[J][r] = -su[g + 4 * r][16 * (J - 1) + c];
+        fin = fin && (J > ntr || __builtin_isfinite(Y[J][r]));
+      }
+    const bool allfin = __ballot(!fin) == 0;
+    const unsigned long long act = __ballot(live && pos >= k0 + wd);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= tr) continue;
+#pragma unroll
+      for (int J = 1; J < 4; ++J) {
+        if (J > ntr) continue;
+        d4 acc = A[t][J];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc = mfma(X[t][r], Y[J][r], acc);
+        if (allfin) {
+          A[t][J] = acc;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if ((act >> (16 * t + g + 4 * r)) & 1) A[t][J][r] = acc[r];
+        }
+      }
+      // the pivot rows take U12 as the substitution formed it (only the
+      // updates of the steps before their own, as in the oracle)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = spos[16 * t + g + 4 * r] - k0;
+        const bool pv = q >= 0 && q < wd;
+        const int qq = pv ? q : 0;
+#pragma unroll
+        for (int J = 1; J < 4; ++J) {
+          if (J > ntr) continue;
+          const double u = su[qq][16 * (J - 1) + c];
+          if (pv) A[t][J][r] = u;
+        }
+      }
+    }
+    wave_sync();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const d4 f = A[t][0];
+      A[t][0] = A[t][1];
+      A[t][1] = A[t][2];
+      A[t][2] = A[t][3];
+      A[t][3] = f;
+    }
+  }
+#pragma unroll 1
+  for (int q = np; q < 4; ++q) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const d4 f = A[t][0];
+      A[t][0] = A[t][1];
+      A[t][1] = A[t][2];
+      A[t][2] = A[t][3];
+      A[t][3] = f;
+    }
+  }
+  // rows to their final positions through LDS: one column per store, the
+  // lanes' rows filling whole panel columns
+#pragma unroll
+  for (int J = 0; J < 4; ++J) {
+    if (J >= tc) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sp[16 * t + g + 4 * r][c] = A[t][J][r];
+    wave_sync();
+    if (live) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (16 * J + j < n) bstore(rD, 8 * (int)pm_off(D.ai + pos, D.aj + 16 * J + j, D.cn), 0, sp[l][j]);
+    }
+    wave_sync();
+  }
+  if (l < mn) {
+    if (ipb) ipb[l] = sipv[l];
+    if (dAb) dAb[l] = sdav[l];
+  }
+  if (info && l == 0) info[b] = inf;
+}
+
 // ---------------------------------------------------------------- getrf, blocked
 // LU with partial pivoting of an m-by-n matrix with max(m, n) > 64 (up to
 // 256), blocked by panels of 16 columns as in §5.2.2 (getrf: a panel
@@ -1098,7 +1453,19 @@ int launch_getrf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
   View D = make_view(sD, di, dj, m, n);
   const dim3 g(1, batch);
   const long long sdA = batch_stride(sD), sip = m < n ? m : n;
-  if (m > 64 || n > 64) {
+  // the one-wave kernel addresses C and D through 32-bit buffer offsets
+  const bool small_bufs = 8LL * ((C.ai + m + 15) & ~15) * C.cn < kOobOffset &&
+                          8LL * ((D.ai + m + 15) & ~15) * D.cn < kOobOffset;
+  if ((m > 32 || n > 32) && (m > 64 || n > 64 || small_bufs)) {
+    if (m <= 64 && n <= 64) {
+      if (pivot)
+        hipLaunchKernelGGL(k_getrf_mf<true>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
+                           batch_stride(sC), batch_stride(sD), sdA, sip);
+      else
+        hipLaunchKernelGGL(k_getrf_mf<false>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
+                           batch_stride(sC), batch_stride(sD), sdA, sip);
+      return launch_status();
+    }
     if (pivot)
       hipLaunchKernelGGL(k_getrf_big<true>, g, dim3(kGetrfBigT), 0, st, m, n, C, D, sD->dA, ipiv,
                          info, batch_stride(sC), batch_stride(sD), sdA, sip);

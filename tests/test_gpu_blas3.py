@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from _util import assert_parity, note
+from _util import TOL, assert_parity, note, rel
 from oracle import panel
 
 pytestmark = pytest.mark.gpu
@@ -311,12 +311,17 @@ def test_dpotrf_l(n, off):
 
 # ------------------------------------------------------------------ getrf
 
-@pytest.mark.parametrize("m,n", [(1, 1), (6, 6), (40, 40), (64, 64), (30, 17), (17, 30), (64, 33)])
+@pytest.mark.parametrize("m,n", [(1, 1), (6, 6), (32, 32), (30, 17), (17, 30), (32, 5),
+                                 (40, 40), (64, 64), (64, 33), (33, 64), (48, 20), (20, 48), (64, 1), (1, 64),
+                                 (37, 61), (61, 37)])
 @pytest.mark.parametrize("pivot", [True, False])
 @pytest.mark.parametrize("off", [(0, 0, 0, 0), (3, 5, 7, 2)])
 def test_dgetrf(m, n, pivot, off):
-    """LU against the oracle: the same interchanges (bit-exact) and the
-    packed L\\U element by element; dA = 1/diag(U); sentinels outside D."""
+    """LU against the oracle: the same interchanges and the packed L\\U
+    element by element; dA = 1/diag(U); sentinels outside D.  Up to order
+    32 (the unblocked kernel) the bits are the oracle's; above (one wave,
+    panels of 16, MFMA trailing update) the factors agree within the parity
+    bound and the GPU's own factors satisfy P C = L U to the same bound."""
     note("getrf", m, n, pivot, off)
     ci, cj, di, dj = off
     rng = np.random.default_rng(m * 3 + n + int(pivot))
@@ -338,10 +343,21 @@ def test_dgetrf(m, n, pivot, off):
         assert np.array_equal(ipiv.cpu().numpy(), ipr)
     assert_parity(Dfull[di:, dj:], Dr, max(m, n), "getrf")
     assert_parity(sD.dA()[:mn].cpu().numpy(), dAr, max(m, n), "dA")
-    # the kernel performs the oracle's operations in the oracle's order, in
-    # IEEE binary64 without contraction on both sides: identical bits
-    assert np.array_equal(Dfull[di:, dj:], Dr)
-    assert np.array_equal(sD.dA()[:mn].cpu().numpy(), dAr)
+    if max(m, n) <= 32:
+        # the kernel performs the oracle's operations in the oracle's order,
+        # in IEEE binary64 without contraction on both sides: identical bits
+        assert np.array_equal(Dfull[di:, dj:], Dr)
+        assert np.array_equal(sD.dA()[:mn].cpu().numpy(), dAr)
+    else:
+        D = Dfull[di:, dj:]
+        L = np.tril(D, -1)[:, :mn] + np.eye(m, mn)
+        U = np.triu(D)[:mn, :]
+        PC = C.copy()
+        if pivot:
+            ip = ipiv.cpu().numpy()
+            for k in range(mn):
+                PC[[k, ip[k]]] = PC[[ip[k], k]]
+        assert_parity(L @ U, PC, max(m, n), "P C = L U")
     mask = np.ones_like(Dfull, dtype=bool)
     mask[di:, dj:] = False
     assert np.all(Dfull[mask] == SENT)
@@ -363,6 +379,67 @@ def test_dgetrf_nan_pivots_as_oracle(where):
     Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=True)
     assert np.array_equal(ipiv.cpu().numpy(), ipr)
     assert np.array_equal(D, Dr, equal_nan=True)
+
+
+@pytest.mark.parametrize("where", [(0, 0), (5, 0), (40, 3), (20, 17), (63, 50), (10, 63)])
+def test_dgetrf_one_wave_nan_as_oracle(where):
+    """Orders 33..64 (one wave, MFMA trailing update): a NaN anywhere gives
+    the oracle's interchanges and NaNs in exactly the oracle's places (rows
+    finished by earlier panels are not touched by later updates)."""
+    note("getrf one-wave nan", where)
+    rng = np.random.default_rng(32)
+    C = rng.standard_normal((64, 64))
+    C[where] = np.nan
+    sC, sD = mat(C), p.DMat(64, 64)
+    ipiv = torch.full((64,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_dgetrf_pivot(64, 64, sC, 0, 0, sD, 0, 0, ipiv)
+    D = host(sD)
+    Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=True)
+    assert np.array_equal(ipiv.cpu().numpy(), ipr), where
+    assert np.array_equal(np.isnan(D), np.isnan(Dr)), where
+    ok = ~np.isnan(Dr)
+    assert_parity(D[ok], Dr[ok], 64, "finite part")
+
+
+def test_dgetrf_one_wave_exact_batched():
+    """Orders 33..64: exact integer factors without pivoting (every
+    intermediate value an integer, so any order of the operations gives the
+    exact factors), in place; a full batch of 64 x 64 against the oracle on
+    every instance (interchanges equal, factors within the parity bound) with
+    one zero pivot reported in info."""
+    note("getrf one-wave exact/batched")
+    rng = np.random.default_rng(94)
+    for (m, n) in [(64, 64), (50, 64), (64, 45)]:
+        mn = min(m, n)
+        Lm = np.tril(rng.integers(-2, 3, (m, mn)), -1) + np.eye(m, mn)
+        U = np.triu(rng.integers(-2, 3, (mn, n)), 1)
+        U[np.arange(mn), np.arange(mn)] = rng.choice([1.0, 2.0, -1.0, 4.0], mn)
+        C = Lm @ U
+        sC = mat(C)
+        p.blasfeo_dgetrf_nopivot(m, n, sC, 0, 0, sC, 0, 0)  # in place
+        D = host(sC)
+        assert np.array_equal(np.tril(D, -1)[:, :mn] + np.eye(m, mn), Lm), (m, n)
+        assert np.array_equal(np.triu(D)[:mn, :], U), (m, n)
+    batch, m = 4096, 64
+    C = rng.standard_normal((batch, m, m))
+    C[9, :, 5] = 0.0
+    sC, sD = p.pack_batch(dev(C)), p.DMatBatch(batch, m, m)
+    info = torch.full((batch,), -1, dtype=torch.int32, device=DEV)
+    ipiv = torch.full((batch, m), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_hip_dgetrf_batched(batch, m, m, sC, 0, 0, sD, 0, 0, 1, ipiv, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    assert inf[9] == 6 and np.sum(inf != 0) == 1
+    D = p.unpack_batch(sD).cpu().numpy()
+    ip = ipiv.cpu().numpy()
+    worst = 0.0
+    for b in range(batch):
+        Dr, ipr, _, infr = oracle.dgetrf(C[b], pivot=True)
+        assert infr == inf[b] and np.array_equal(ip[b], ipr), b
+        if b != 9:
+            worst = max(worst, rel(D[b], Dr))
+    print(f"getrf 4096 x 64x64: worst rel Frobenius error {worst:.3e}")
+    assert worst <= TOL * m
 
 
 def test_dgetrf_exact_batched_info_and_errors():
