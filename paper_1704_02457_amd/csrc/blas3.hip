@@ -718,17 +718,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) A[t][0][r] = sp[16 * t + g + 4 * r][c];
-    d4 X[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int ps = spos[16 * t + c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = g + 4 * r;
-        X[t][r] = *((j < wd && ps >= k0 + wd) ? &sp[16 * t + c][j] : &szero);
-      }
-    }
-    wave_sync();
     if (ntr > 0) {
     // (b) A12 of the pivot rows: each lane writes the entries of its rows,
     // a pivot row's to its row of su and the others' to a row past the
@@ -761,10 +750,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int kk = 0; kk < 16; ++kk) su[kk][l] = kk < wd ? x[kk] : 0.0;
     }
     wave_sync();
-    // (c) the trailing update of the rows below the panel's pivot rows
-    // (their rows of X are the multipliers, every other row's zero: with a
-    // finite U12 the product leaves those rows as they are, up to the sign
-    // of a zero; otherwise their values are kept by a select)
+    // (c) the trailing update.  With a finite U12 (the usual case) every
+    // row's multipliers of the steps before its own position go into X, so
+    // that the rows below the pivot rows take the whole update, each pivot
+    // row the updates of the steps before its own (its row of U12, to
+    // rounding) and every other row a zero update (its values kept, up to
+    // the sign of a zero).  Otherwise only the rows below the pivot rows are
+    // updated, by a select, and the pivot rows take U12 from LDS, as in the
+    // oracle a non-finite U12 entry never reaches a finished row.
     d4 Y[4];
     bool fin = true;
 #pragma unroll
@@ -775,6 +768,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         fin = fin && (J > ntr || __builtin_isfinite(Y[J][r]));
       }
     const bool allfin = __ballot(!fin) == 0;
+    // X: row i's multipliers of the steps j it takes (rows at positions
+    // above k0 + j with a finite U12, rows below the pivot rows otherwise)
+    const int xlo = allfin ? k0 : k0 + wd - 1;
+    d4 X[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ps = spos[16 * t + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = g + 4 * r;
+        X[t][r] = *((j < wd && ps > xlo + (allfin ? j : 0)) ? &sp[16 * t + c][j] : &szero);
+      }
+    }
     const unsigned long long act = __ballot(live && pos >= k0 + wd);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -793,18 +799,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             if ((act >> (16 * t + g + 4 * r)) & 1) A[t][J][r] = acc[r];
         }
       }
-      // the pivot rows take U12 as the substitution formed it (only the
-      // updates of the steps before their own, as in the oracle)
+    }
+    if (!allfin) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = spos[16 * t + g + 4 * r] - k0;
-        const bool pv = q >= 0 && q < wd;
-        const int qq = pv ? q : 0;
+      for (int t = 0; t < 4; ++t) {
+        if (t >= tr) continue;
 #pragma unroll
-        for (int J = 1; J < 4; ++J) {
-          if (J > ntr) continue;
-          const double u = su[qq][16 * (J - 1) + c];
-          if (pv) A[t][J][r] = u;
+        for (int r = 0; r < 4; ++r) {
+          const int q = spos[16 * t + g + 4 * r] - k0;
+          const bool pv = q >= 0 && q < wd;
+          const int qq = pv ? q : 0;
+#pragma unroll
+          for (int J = 1; J < 4; ++J) {
+            if (J > ntr) continue;
+            const double u = su[qq][16 * (J - 1) + c];
+            if (pv) A[t][J][r] = u;
+          }
         }
       }
     }
