@@ -360,6 +360,8 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
             "gelqf_64_batch_gflops": round(batch * (4.0 / 3.0) * nl ** 3 / m4 / 1e6, 1),
             "getrf_pivot_64_batch_ms": round(m3, 4),
             "getrf_pivot_64_batch_gflops": round(batch * (2.0 / 3.0) * nl ** 3 / m3 / 1e6, 1),
+            "getrf_pivot_64_batch_config": f"{batch} x {nl}x{nl}, one wave per instance (matrix in registers, "
+                                           "panels of 16, MFMA trailing update)",
             "stacked_potrf_l_mn_ms": round(m1, 4), "stacked_potrf_l_mn_gflops": round(batch * fl1 / m1 / 1e6, 1),
             "range_space_schur_chol_ms": round(m2, 4),
             "range_space_chain_ms": round(m1 + m2, 4),

@@ -612,8 +612,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int j = 0; j < 16; ++j) pr[j] = sp[l][j];
     wave_sync();
-    int ipv = 0;  // step l's pivot position and reciprocal
-    double dav = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       if (kk >= wd) continue;
@@ -622,51 +620,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       int pl = k, ppos = k;
       if (PIVOT) {
         // the oracle's scan keeps position k unless a later row is strictly
-        // larger: a NaN there wins and a NaN elsewhere never does (keys:
-        // |v| for the candidates, +inf for a NaN at position k, below zero
-        // for a NaN elsewhere and for the other rows).  The wave max runs on
-        // the keys rounded to binary32 (a rounding that keeps their order,
-        // ties aside): a single lane at the maximum is the pivot; several
-        // are resolved by their binary64 keys, then by position.
-        const double av = __builtin_isnan(v) ? (pos == k ? __builtin_inf() : -0.5) : fabs(v);
-        const bool cand = live && pos >= k;
-        const float kf = cand ? (float)av : -1.0f;
-        float x = kf;
-        asm volatile(
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-            "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
-            "s_nop 1"
-            : "+v"(x));
-        const float mxf = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
-        unsigned long long hit = __ballot(cand && kf == mxf);
-        if (hit & (hit - 1)) {
-          const bool h = (hit >> l) & 1;
-          double y = h ? av : -1.0;
-          y = dpp_max_step<0x111>(y);
-          y = dpp_max_step<0x112>(y);
-          y = dpp_max_step<0x114>(y);
-          y = dpp_max_step<0x118>(y);
-          y = dpp_max_step<0x142>(y);
-          y = dpp_max_step<0x143>(y);
-          const double mx = readlane_d(y, 63);
-          hit = __ballot(h && av == mx);
+        // larger: a NaN at position k is the pivot, a NaN elsewhere never
+        // is.  Otherwise the wave max runs on |v| rounded to binary32 (a
+        // rounding that keeps the order, ties aside; NaN keys drop out of
+        // the max): a single lane at the maximum is the pivot, several are
+        // resolved by their binary64 values, then by position.
+        const int kl = __builtin_ctzll(__ballot(live && pos == k));
+        const bool knan = __builtin_isnan(readlane_d(v, kl));
+        {
+          const bool cand = live && pos >= k;
+          const float kf = cand ? (float)fabs(v) : -1.0f;
+          float x = kf;
+          asm volatile(
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+              "s_nop 1"
+              : "+v"(x));
+          const float mxf = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+          unsigned long long hit = __ballot(cand && kf == mxf);
+          if (hit & (hit - 1)) {
+            const bool h = (hit >> l) & 1;
+            double y = h ? fabs(v) : -1.0;
+            y = dpp_max_step<0x111>(y);
+            y = dpp_max_step<0x112>(y);
+            y = dpp_max_step<0x114>(y);
+            y = dpp_max_step<0x118>(y);
+            y = dpp_max_step<0x142>(y);
+            y = dpp_max_step<0x143>(y);
+            const double mx = readlane_d(y, 63);
+            hit = __ballot(h && fabs(v) == mx);
+          }
+          pl = __builtin_ctzll(hit);
+          if (hit & (hit - 1)) {
+            int q = (hit >> l) & 1 ? pos : 0x7fffffff;
+            q = dpp_min_step<0x111, 0xf>(q);
+            q = dpp_min_step<0x112, 0xf>(q);
+            q = dpp_min_step<0x114, 0xf>(q);
+            q = dpp_min_step<0x118, 0xf>(q);
+            q = dpp_min_step<0x142, 0xa>(q);
+            q = dpp_min_step<0x143, 0xc>(q);
+            const int best = __builtin_amdgcn_readlane(q, 63);
+            pl = __builtin_ctzll(__ballot(live && pos == best));
+          }
         }
-        pl = __builtin_ctzll(hit);
-        if (hit & (hit - 1)) {
-          int q = (hit >> l) & 1 ? pos : 0x7fffffff;
-          q = dpp_min_step<0x111, 0xf>(q);
-          q = dpp_min_step<0x112, 0xf>(q);
-          q = dpp_min_step<0x114, 0xf>(q);
-          q = dpp_min_step<0x118, 0xf>(q);
-          q = dpp_min_step<0x142, 0xa>(q);
-          q = dpp_min_step<0x143, 0xc>(q);
-          const int best = __builtin_amdgcn_readlane(q, 63);
-          pl = __builtin_ctzll(__ballot(live && pos == best));
-        }
+        if (knan) pl = kl;
         ppos = __builtin_amdgcn_readlane(pos, pl);
         if (pos == k) pos = ppos;
         if (l == pl) pos = k;
@@ -674,20 +675,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const double piv = readlane_d(v, pl);
       if (piv == 0.0 && inf == 0) inf = k + 1;
       // 1/piv: the hardware reciprocal and two Newton steps (within an ulp)
-      // for pivots of moderate magnitude, the division otherwise (zero,
-      // infinite, NaN or extreme pivots keep the oracle's special values)
+      // for pivots of moderate magnitude (binary exponent within +-1000),
+      // the division otherwise (zero, infinite, NaN or extreme pivots keep
+      // the oracle's special values)
       double invp;
-      const double ap = fabs(piv);
-      if (ap > 0x1p-1000 && ap < 0x1p1000) {
+      const unsigned int pex = (unsigned int)(__builtin_bit_cast(unsigned long long, piv) >> 52) & 0x7ffu;
+      if (pex > 23u && pex < 2023u) {
         double r = __builtin_amdgcn_rcp(piv);
         r = fma(r, fma(-piv, r, 1.0), r);
         invp = fma(r, fma(-piv, r, 1.0), r);
       } else {
         invp = 1.0 / piv;
       }
-      if (l == kk) {
-        ipv = ppos;
-        dav = invp;
+      if (l == 0) {
+        sipv[k] = ppos;
+        sdav[k] = invp;
       }
       double pc[16];
 #pragma unroll
@@ -698,10 +700,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
         for (int j = kk + 1; j < 16; ++j) pr[j] = fma(-mult, pc[j], pr[j]);
       }
-    }
-    if (l < wd) {
-      sipv[k0 + l] = ipv;
-      sdav[k0 + l] = dav;
     }
     // the panel back into its column tile; the multipliers (transposed, for
     // the MFMA's left operand), the pivot rows and the positions to LDS
