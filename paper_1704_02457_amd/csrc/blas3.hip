@@ -511,7 +511,8 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
 //       is the row of largest magnitude among positions >= k (a wave max on
 //       DPP, ties to the smallest position), the pivot row's entries reach
 //       the other lanes by readlane, and each row below forms its
-//       multiplier and updates the panel's remaining columns;
+//       multiplier and updates the panel's remaining columns; the finished
+//       panel then stays in its tile's registers as one row per lane;
 //   (b) the pivot rows' entries right of the panel (A12, written to LDS by
 //       the lanes holding them) give U12 = L11^{-1} A12 by forward
 //       substitution, one lane per column;
@@ -712,10 +713,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int j = 0; j < 16; ++j) slT[j][kp] = pr[j];
     }
     wave_sync();
+    // the finished panel stays in its column tile's registers as the lane's
+    // row (register r of tile t holds column 4t + r): rows are what the
+    // final stores take
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) A[t][0][r] = sp[16 * t + g + 4 * r][c];
+      for (int r = 0; r < 4; ++r) A[t][0][r] = pr[4 * t + r];
     if (ntr > 0) {
     // (b) A12 of the pivot rows: each lane writes the entries of its rows,
     // a pivot row's to its row of su and the others' to a row past the
@@ -838,22 +842,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       A[t][3] = f;
     }
   }
-  // rows to their final positions through LDS: one column per store, the
-  // lanes' rows filling whole panel columns
+  // rows to their final positions, one column per store so that the
+  // lanes' rows fill whole panel columns: the factored column tiles hold
+  // rows already, the others (columns right of the last panel) go through
+  // LDS
 #pragma unroll
   for (int J = 0; J < 4; ++J) {
     if (J >= tc) continue;
+    if (J < np) {
+      if (live) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int j = 0; j < 16; ++j)
+          if (16 * J + j < n)
+            bstore(rD, 8 * (int)pm_off(D.ai + pos, D.aj + 16 * J + j, D.cn), 0, A[j >> 2][J][j & 3]);
+      }
+    } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sp[16 * t + g + 4 * r][c] = A[t][J][r];
-    wave_sync();
-    if (live) {
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (16 * J + j < n) bstore(rD, 8 * (int)pm_off(D.ai + pos, D.aj + 16 * J + j, D.cn), 0, sp[l][j]);
+        for (int r = 0; r < 4; ++r) sp[16 * t + g + 4 * r][c] = A[t][J][r];
+      wave_sync();
+      if (live) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (16 * J + j < n) bstore(rD, 8 * (int)pm_off(D.ai + pos, D.aj + 16 * J + j, D.cn), 0, sp[l][j]);
+      }
+      wave_sync();
     }
-    wave_sync();
   }
   if (l < mn) {
     if (ipb) ipb[l] = sipv[l];
