@@ -613,9 +613,73 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int j = 0; j < 16; ++j) pr[j] = sp[l][j];
     wave_sync();
+    // A full panel whose entries are all finite and below 2^1000 in
+    // magnitude first takes a sweep without branches (its steps overlap in
+    // the instruction schedule): partial pivoting keeps every multiplier at
+    // most 1, so the panel stays finite unless a pivot is zero, and a row
+    // that is not below the pivot may take a zero update.  A zero, tiny or
+    // huge pivot or a tie for the maximum (in binary32) marks the sweep as
+    // unusable; the panel is then read again from LDS and swept with the
+    // branches below.
+    bool safe = true;
+    if (PIVOT && wd == 16) {
+      bool okl = true;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) okl = okl && fabs(pr[j]) < 0x1p1000;
+      if (__ballot(!okl) == 0) {
+        const int pos0 = pos;
+        bool bad = false;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const int k = k0 + kk;
+          const double v = pr[kk];
+          const bool cand = live && pos >= k;
+          const float kf = cand ? (float)fabs(v) : -1.0f;
+          float x = kf;
+          asm volatile(
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+              "s_nop 1\n\tv_max_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+              "s_nop 1"
+              : "+v"(x));
+          const float mxf = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+          const unsigned long long hit = __ballot(cand && kf == mxf);
+          const int pl = __builtin_ctzll(hit);
+          const int ppos = __builtin_amdgcn_readlane(pos, pl);
+          pos = pos == k ? ppos : pos;
+          pos = l == pl ? k : pos;
+          const double piv = readlane_d(v, pl);
+          const unsigned int pex = (unsigned int)(__builtin_bit_cast(unsigned long long, piv) >> 52) & 0x7ffu;
+          bad = bad || (hit & (hit - 1)) != 0 || pex <= 23u || pex >= 2023u;
+          double r = __builtin_amdgcn_rcp(piv);
+          r = fma(r, fma(-piv, r, 1.0), r);
+          const double invp = fma(r, fma(-piv, r, 1.0), r);
+          sipv[k] = ppos;  // (every lane stores the same value)
+          sdav[k] = invp;
+          double pc[16];
+#pragma unroll
+          for (int j = kk + 1; j < 16; ++j) pc[j] = readlane_d(pr[j], pl);
+          const bool below = live && pos > k;
+          const double mult = v * invp;
+          const double mm = below ? mult : 0.0;
+          pr[kk] = below ? mult : pr[kk];
+#pragma unroll
+          for (int j = kk + 1; j < 16; ++j) pr[j] = fma(-mm, pc[j], pr[j]);
+        }
+        safe = bad;
+        if (bad) {
+          pos = pos0;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) pr[j] = sp[l][j];
+        }
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      if (kk >= wd) continue;
+      if (!safe || kk >= wd) continue;
       const int k = k0 + kk;
       const double v = pr[kk];
       int pl = k, ppos = k;

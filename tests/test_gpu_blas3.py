@@ -401,6 +401,40 @@ def test_dgetrf_one_wave_nan_as_oracle(where):
     assert_parity(D[ok], Dr[ok], 64, "finite part")
 
 
+@pytest.mark.parametrize("case", ["exact_tie", "binary32_tie", "tiny_pivot", "huge"])
+def test_dgetrf_one_wave_ties_and_extremes(case):
+    """Orders 33..64 with pivoting: cases that a panel's first, branch-free
+    sweep hands back to the exact sweep -- an exact tie for the largest
+    magnitude (the first row wins), two magnitudes equal in binary32 but
+    not in binary64 (the larger wins), a pivot below 2^-1000 and entries
+    above 2^1000 -- give the oracle's interchanges and factors."""
+    note("getrf one-wave ties", case)
+    rng = np.random.default_rng(41)
+    C = rng.uniform(-1.0, 1.0, (64, 64))
+    if case == "exact_tie":
+        C[[5, 9, 20], 0] = [3.0, -3.0, 3.0]
+        C[[30, 31], 17] = [-50.0, 50.0]
+    elif case == "binary32_tie":
+        C[3, 0], C[7, 0] = 4.0, -(4.0 + 2.0 ** -38)
+        C[40, 20], C[22, 20] = 9.0 + 2.0 ** -35, 9.0
+    elif case == "tiny_pivot":
+        C[:, 2] *= 2.0 ** -1010
+    else:
+        C[10:, 40:] *= 2.0 ** 1005
+    sC, sD = mat(C), p.DMat(64, 64)
+    ipiv = torch.full((64,), -1, dtype=torch.int32, device=DEV)
+    p.blasfeo_dgetrf_pivot(64, 64, sC, 0, 0, sD, 0, 0, ipiv)
+    D = host(sD)
+    Dr, ipr, dAr, inf = oracle.dgetrf(C, pivot=True)
+    assert np.array_equal(ipiv.cpu().numpy(), ipr), case
+    assert np.all(np.isfinite(D)) and np.all(np.isfinite(Dr))
+    sc = np.abs(Dr).max()  # (the Frobenius norm of the huge case overflows)
+    assert_parity(D / sc, Dr / sc, 64, case)
+    dA = sD.dA()[:64].cpu().numpy()
+    sa = np.abs(dAr).max()
+    assert_parity(dA / sa, dAr / sa, 64, "dA " + case)
+
+
 def test_dgetrf_one_wave_exact_batched():
     """Orders 33..64: exact integer factors without pivoting (every
     intermediate value an integer, so any order of the operations gives the
