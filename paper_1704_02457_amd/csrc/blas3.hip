@@ -588,7 +588,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const int off = (i < m && j < n) ? 8 * (int)pm_off(C.ai + i, C.aj + j, C.cn) : kOobOffset;
         A[t][J][r] = bload(rC, off, 0);
       }
-  __builtin_amdgcn_s_waitcnt(0);
   const bool live = l < m;
   int pos = l;
   int inf = 0;
