@@ -511,15 +511,19 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
 //       is the row of largest magnitude among positions >= k (a wave max on
 //       DPP, ties to the smallest position), the pivot row's entries reach
 //       the other lanes by readlane, and each row below forms its
-//       multiplier and updates the panel's remaining columns; the finished
-//       panel then stays in its tile's registers as one row per lane;
+//       multiplier and updates the panel's remaining columns (a full,
+//       finite panel is swept first without branches and swept again with
+//       them only if a pivot or a tie rules the first sweep out); the
+//       finished panel then stays in its tile's registers as one row per
+//       lane;
 //   (b) the pivot rows' entries right of the panel (A12, written to LDS by
 //       the lanes holding them) give U12 = L11^{-1} A12 by forward
 //       substitution, one lane per column;
-//   (c) every row below the panel's pivot rows: A[i, right] -= L[i, panel]
-//       U12 on the f64 MFMA (L[i, j] the multiplier of row i at step j); the
-//       pivot rows take their rows of U12, and rows finished by earlier
-//       panels keep their values.
+//   (c) the trailing update on the f64 MFMA: every row takes the
+//       multipliers of the steps before its own position times U12, so that
+//       the rows below the pivot rows take the whole update, the pivot rows
+//       their rows of U12 and the rows finished by earlier panels nothing
+//       (a non-finite U12 is handled by selects instead).
 // The oracle's operations with the updates right of a panel delayed to (c)
 // and fused multiply-adds: the factors agree to rounding, the interchanges
 // wherever the pivot candidates differ by more than the rounding, and on
