@@ -358,6 +358,8 @@ def bench_stacking(p, torch, batch=16384, n=40, ma=8, reps=10):
             "gelqf_256_batch_gflops": round(bb * (4.0 / 3.0) * nb ** 3 / m7 / 1e6, 1),
             "gelqf_64_batch_ms": round(m4, 4),
             "gelqf_64_batch_gflops": round(batch * (4.0 / 3.0) * nl ** 3 / m4 / 1e6, 1),
+            "gelqf_64_batch_config": f"{batch} x {nl}x{nl}, one wave per instance (matrix in registers, "
+                                     "panels of 16 rows, MFMA block update)",
             "getrf_pivot_64_batch_ms": round(m3, 4),
             "getrf_pivot_64_batch_gflops": round(batch * (2.0 / 3.0) * nl ** 3 / m3 / 1e6, 1),
             "getrf_pivot_64_batch_config": f"{batch} x {nl}x{nl}, one wave per instance (matrix in registers, "

@@ -210,10 +210,11 @@ void blasfeo_dgetrf_nopivot(int m, int n, struct blasfeo_dmat *sC, int ci,
  * and below the diagonal of D, reflector k's vector to the right of the
  * diagonal of row k (its k-th entry 1 implicit), tau_k in sD->dA[k]
  * (min(m,n) entries); Q = H_{min-1} ... H_0 with H_k = I - tau_k v v'.
- * m, n <= 64: unblocked, the oracle's operations in its order (identical
+ * m, n <= 32: unblocked, the oracle's operations in its order (identical
  * bits); larger: blocked by panels of 16 rows, the rows below a panel
- * updated as A2 -= ((A2 V^T) T) V on the matrix cores (the factors agree to
- * rounding).  Errors: -1 m, -2 n (outside 0..256), -3 C, -6 D (or a NULL
+ * updated as A2 -= ((A2 V^T) T) V on the matrix cores (one wave per
+ * instance with the matrix in registers up to 64, a workgroup per instance
+ * above; the factors agree to rounding).  Errors: -1 m, -2 n (outside 0..256), -3 C, -6 D (or a NULL
  * dA).  C and D may be the same matrix at the same offsets. */
 void blasfeo_dgelqf(int m, int n, struct blasfeo_dmat *sC, int ci, int cj,
                     struct blasfeo_dmat *sD, int di, int dj);

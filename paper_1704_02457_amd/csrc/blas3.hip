@@ -1224,6 +1224,250 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
   if (info && threadIdx.x == 0) info[b] = inf;
 }
 
+// ---------------------------------------------------------------- gelqf, one wave, MFMA
+// LQ factorization (LAPACK's compact form, as the oracle's) of an m-by-n
+// matrix with 32 < max(m, n) <= 64, blocked by panels of 16 rows as in
+// §5.2.2 (gelqf), one wave per instance.  The matrix is held transposed in
+// registers, as 16 T-tiles of A^T (register r of lane (c, g) of tile AT[j][i]
+// holds A[16i + c][16j + g + 4r]), so that the block update of the rows below
+// a panel is three T-tile products on the f64 MFMA.  Per panel of rows
+// k0..k0+15:
+//   (a) the panel goes through LDS to lane i + 16q holding row k0 + i,
+//       columns 16q..16q+15 (16 registers); for each of its rows k: the
+//       squared norm right of column k and every row's product with the
+//       reflector are sums of four lanes' parts (lane shuffles), the
+//       oracle's scalars follow, and the reflector reaches the lanes of each
+//       column quarter by a DPP row broadcast; the rows below it in the panel
+//       subtract; the finished rows are stored at once (later panels do not
+//       touch them);
+//   (b) the reflectors V (unit leading entry) go to LDS, their Gram matrix
+//       V V^T is formed on the MFMA and T (H_0 ... H_15 = I - V^T T V) by the
+//       forward recurrence, one lane per row of T;
+//   (c) every row tile below: A2 -= ((A2 V^T) T) V, as W^T = V A2^T,
+//       Z^T = T^T W^T and A2^T -= V^T Z^T on the MFMA.
+// The row tiles rotate by one per panel so that the panel is always AT[.][0]
+// (the loop's body once in the code).  The oracle's reflectors with the sums
+// in another order: the factors agree to rounding.
+__device__ __forceinline__ int newbcast_i(int x, int kk) {
+  switch (kk) {  // kk is a constant where this is called
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xf, 0xf, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xf, 0xf, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xf, 0xf, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xf, 0xf, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xf, 0xf, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xf, 0xf, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15a, 0xf, 0xf, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15b, 0xf, 0xf, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15c, 0xf, 0xf, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15d, 0xf, 0xf, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15e, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x15f, 0xf, 0xf, false);
+  }
+}
+
+// lane kk's value of each row of 16 lanes, to that row's every lane
+__device__ __forceinline__ double newbcast_d(double x, int kk) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = newbcast_i((int)b, kk), hi = newbcast_i((int)(b >> 32), kk);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the four lanes l, l^16, l^32, l^48
+__device__ __forceinline__ double quarter_sum(double x) {
+  x += __shfl_xor(x, 16);
+  x += __shfl_xor(x, 32);
+  return x;
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_gelqf_mf(
+    int m, int n, View C, View D, double *tau, long long sC, long long sD, long long stau) {
+  C = at_batch(C, sC);
+  D = at_batch(D, sD);
+  const long long b = blockIdx.y;
+  double *taub = tau + b * stau;
+  __shared__ double sp[64][17];  // the panel: [column][row]
+  __shared__ double sv[16][65];  // V: [reflector][column]
+  __shared__ double sg[16][17];  // the Gram matrix, then T
+  __shared__ double stk[16];     // tau of the panel's steps
+  const int l = lane_id();
+  const int c = l & 15, g = l >> 4;  // also (row i, column quarter q) of the panel sweep
+  const int mn = min(m, n);
+  const int tr = (m + 15) >> 4;
+  const brsrc rC = make_rsrc(C.p, 8LL * ((C.ai + m + 15) & ~15) * C.cn);
+  const brsrc rD = make_rsrc(D.p, 8LL * ((D.ai + m + 15) & ~15) * D.cn);
+  // A^T in registers; an element outside the matrix reads as zero (an
+  // offset past the end of the buffer)
+  d4 AT[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + c, col = 16 * j + g + 4 * r;
+        const int off = (row < m && col < n) ? 8 * (int)pm_off(C.ai + row, C.aj + col, C.cn) : kOobOffset;
+        AT[j][i][r] = bload(rC, off, 0);
+      }
+  const int np = (mn + 15) >> 4;
+  // the panel loop is unrolled: a row tile's registers are dead once it has
+  // been a panel (its rows are stored from the sweep) or, below the last
+  // panel (m > n), once it is stored
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p >= np) {
+      if (p < tr) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * p + c, col = 16 * j + g + 4 * r;
+            if (row < m && col < n) bstore(rD, 8 * (int)pm_off(D.ai + row, D.aj + col, D.cn), 0, AT[j][p][r]);
+          }
+      }
+      continue;
+    }
+    const int k0 = 16 * p;
+    const int wd = min(16, mn - k0);
+    const int ntr = tr - 1 - p;  // row tiles below the panel
+    // (a) the panel, lane i + 16q holding row k0 + i, columns 16q + jj
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sp[16 * j + g + 4 * r][c] = AT[j][p][r];
+    }
+    wave_sync();
+    double pr[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) pr[jj] = sp[16 * g + jj][c];
+    wave_sync();
+    const bool qgt = g > p, qge = g >= p;  // quarter right of / holding the diagonal
+    const bool liverow = k0 + c < m;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      if (kk >= wd) continue;
+      // row kk's squared norm right of column k0 + kk
+      double ps = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const bool in = jj > kk ? qge : qgt;
+        ps = in ? fma(pr[jj], pr[jj], ps) : ps;
+      }
+      ps = quarter_sum(ps);
+      const double xn2 = readlane_d(ps, kk);
+      const double alpha = readlane_d(pr[kk], kk + 16 * p);
+      double tk = 0.0, scale = 0.0, beta = alpha;
+      if (sqrt(xn2) != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (l == 0) stk[kk] = tk;
+      // the reflector (v = 0 left of column k, 1 at it) from row kk's lanes
+      // to every lane of the same column quarter
+      double vb[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const bool right = jj > kk ? qge : qgt, at = jj == kk && g == p;
+        const double vv = right ? pr[jj] * scale : (at ? 1.0 : 0.0);
+        vb[jj] = newbcast_d(vv, kk);
+      }
+      if (c == kk) {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          const bool right = jj > kk ? qge : qgt, at = jj == kk && g == p;
+          pr[jj] = right ? vb[jj] : (at ? beta : pr[jj]);
+        }
+      }
+      // the rows below: w = tau (row . v), row -= w v
+      double d = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) d = fma(pr[jj], vb[jj], d);
+      d = quarter_sum(d);
+      if (liverow && c > kk) {
+        const double w = tk * d;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) pr[jj] = fma(-w, vb[jj], pr[jj]);
+      }
+    }
+    // the finished rows to D (one column per store: whole panel columns),
+    // tau, and the reflectors to LDS for the block update
+    if (liverow) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj)
+        if (16 * g + jj < n) bstore(rD, 8 * (int)pm_off(D.ai + k0 + c, D.aj + 16 * g + jj, D.cn), 0, pr[jj]);
+    }
+    wave_sync();
+    if (l < wd) taub[k0 + l] = stk[l];
+    if (ntr > 0) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int col = 16 * g + jj, kc = k0 + c;
+        sv[c][col] = (c < wd && col > kc) ? pr[jj] : ((c < wd && col == kc) ? 1.0 : 0.0);
+      }
+      wave_sync();
+      // (b) G = V V^T, then T, one lane per row
+      d4 G = zero4();
+#pragma unroll
+      for (int J = p; J < 4; ++J) {
+        d4 VT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) VT[r] = sv[c][16 * J + g + 4 * r];
+        G = mfma_tn(VT, VT, G);
+      }
+      // T = (I + diag(tau) striu(G))^{-1} diag(tau): the inverse of T is
+      // diag(1/tau) + striu(G) (the forward recurrence in closed form),
+      // written without dividing by tau so that a zero tau (an identity
+      // reflector) needs no care; the unit upper triangular inverse by the
+      // register back substitution (sp as its staging area)
+      d4 U;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = g + 4 * r;
+        U[r] = c > a ? stk[a] * G[r] : (c == a ? 1.0 : 0.0);
+      }
+      if (l < 16) sg[1][l] = 1.0;
+      wave_sync();
+      const d4 Vi = trtri_tile_upper(U, &sg[1][0], &sp[0][0], &sg[0][0]);
+      d4 TT;
+      const double tc = stk[c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) TT[r] = Vi[r] * tc;
+      // (c) W^T = V A2^T and Z^T = T^T W^T for every row tile below
+      d4 Zt[3];
+#pragma unroll
+      for (int i = p + 1; i < 4; ++i) {
+        if (i >= tr) continue;
+        d4 Wt = zero4();
+#pragma unroll
+        for (int J = p; J < 4; ++J) {
+          d4 VT;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) VT[r] = sv[c][16 * J + g + 4 * r];
+          Wt = mfma_tn(VT, AT[J][i], Wt);
+        }
+        Zt[i - p - 1] = -mfma_tn(TT, Wt, zero4());
+      }
+      // A2^T -= V^T Z^T, one column tile of V at a time
+#pragma unroll
+      for (int J = p; J < 4; ++J) {
+        d4 VN;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) VN[r] = sv[g + 4 * r][16 * J + c];
+#pragma unroll
+        for (int i = p + 1; i < 4; ++i) {
+          if (i >= tr) continue;
+          AT[J][i] = mfma_tn(VN, Zt[i - p - 1], AT[J][i]);
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- gelqf, blocked
 // LQ factorization (Householder reflectors, LAPACK's compact form) of an
 // m-by-n matrix with max(m, n) > 64 (up to 256), blocked by panels of 16
@@ -1522,8 +1766,14 @@ int launch_gelqf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
   if (batch == 0 || m == 0 || n == 0) return 0;
   View C = make_view(sC, ci, cj, m, n);
   View D = make_view(sD, di, dj, m, n);
+  // the one-wave kernel addresses C and D through 32-bit buffer offsets
+  const bool small_bufs = 8LL * ((C.ai + m + 15) & ~15) * C.cn < kOobOffset &&
+                          8LL * ((D.ai + m + 15) & ~15) * D.cn < kOobOffset;
   if (m > 64 || n > 64)
     hipLaunchKernelGGL(k_gelqf_big, dim3(1, batch), dim3(kGelqfBigT), 0, st, m, n, C, D, sD->dA,
+                       batch_stride(sC), batch_stride(sD), batch_stride(sD));
+  else if ((m > 32 || n > 32) && small_bufs)
+    hipLaunchKernelGGL(k_gelqf_mf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
                        batch_stride(sC), batch_stride(sD), batch_stride(sD));
   else
     hipLaunchKernelGGL(k_gelqf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
