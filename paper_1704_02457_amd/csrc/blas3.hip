@@ -1276,11 +1276,30 @@ __device__ __forceinline__ double newbcast_d(double x, int kk) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// sum over the four lanes l, l^16, l^32, l^48
+// sum over the four lanes l, l^16, l^32, l^48 with the row swaps of gfx950:
+// permlane16_swap of (x, x) leaves rows (0,0,2,2) in one register and
+// (1,1,3,3) in the other, whose sum is x + x[l^16]; permlane32_swap does the
+// same with rows (0,1,0,1) and (2,3,2,3)
+__device__ __forceinline__ double swap_sum(double x, bool by32) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  unsigned a0, a1, h0, h1;
+  if (by32) {
+    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a0 = pl[0]; a1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+  } else {
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a0 = pl[0]; a1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+  }
+  const double u = __builtin_bit_cast(double, ((unsigned long long)h0 << 32) | a0);
+  const double v = __builtin_bit_cast(double, ((unsigned long long)h1 << 32) | a1);
+  return u + v;
+}
+
 __device__ __forceinline__ double quarter_sum(double x) {
-  x += __shfl_xor(x, 16);
-  x += __shfl_xor(x, 32);
-  return x;
+  return swap_sum(swap_sum(x, false), true);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_gelqf_mf(
