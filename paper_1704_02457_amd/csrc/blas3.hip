@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(kGetrfBigT) __attribute__((amdgpu_waves_per_eu(4)))
 //   (a) the panel goes through LDS to lane i + 16q holding row k0 + i,
 //       columns 16q..16q+15 (16 registers); for each of its rows k: the
 //       squared norm right of column k and every row's product with the
-//       reflector are sums of four lanes' parts (lane shuffles), the
+//       reflector are sums of four lanes' parts (row swaps), the
 //       oracle's scalars follow, and the reflector reaches the lanes of each
 //       column quarter by a DPP row broadcast; the rows below it in the panel
 //       subtract; the finished rows are stored at once (later panels do not
