@@ -410,8 +410,8 @@ __device__ __forceinline__ void argmax_step(double &key, int &pos) {
 // ---------------------------------------------------------------- getrf
 // LU with (PIVOT) or without partial pivoting of an m-by-n matrix, m, n <=
 // 64 (§5.2.2, getrf): one wave per instance with lane i holding row i of
-// the matrix in 64 registers, the right-looking unblocked sweep of the
-// oracle.  Rows are never moved: each lane keeps the current position of its
+// the matrix in NC registers (n rounded up to 16), the right-looking
+// unblocked sweep of the oracle.  Rows are never moved: each lane keeps the current position of its
 // row, an interchange swaps two positions, and the rows are stored to their
 // final positions at the end.  Step k: the pivot is the row of largest
 // magnitude in column k among positions >= k, ties to the smallest position
@@ -423,7 +423,7 @@ __device__ __forceinline__ void argmax_step(double &key, int &pos) {
 // in register 16*qb + kk: the 16 steps of a block of columns select it from
 // the block's 16 registers, and the update runs over the columns from the
 // block on, so registers are indexed at compile time.
-template <bool PIVOT>
+template <bool PIVOT, int NC>
 __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, double *dA,
                                               int *ipiv, int *info, long long sC,
                                               long long sD, long long sdA, long long sip) {
@@ -436,9 +436,9 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   const int l = lane_id();
   const bool live = l < m;
   const int lr = min(l, m - 1);
-  double r[64];
+  double r[NC];  // NC: n rounded up to a multiple of 16
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
+  for (int c = 0; c < NC; ++c) {
     const double x = C.p[pm_off(C.ai + lr, C.aj + min(c, n - 1), C.cn)];  // clamped: no branch
     r[c] = (live && c < n) ? x : 0.0;
   }
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   int inf = 0;
   const int mn = min(m, n);
 #pragma unroll
-  for (int qb = 0; qb < 4; ++qb) {
+  for (int qb = 0; qb < NC / 16; ++qb) {
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 16 * qb + kk;
       if (k >= mn) break;
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
 #pragma unroll
       for (int e = 0; e < 16; ++e) r[16 * qb + e] = (below && kk == e) ? mult : r[16 * qb + e];
 #pragma unroll
-      for (int c = 16 * qb; c < 64; ++c) {
+      for (int c = 16 * qb; c < NC; ++c) {
         if (c < n) {
           const double pc = readlane_d(r[c], pl);
           const double upd = r[c] - mult * pc;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(64) void k_getrf(int m, int n, View C, View D, doub
   }
   if (live) {
 #pragma unroll
-    for (int c = 0; c < 64; ++c)
+    for (int c = 0; c < NC; ++c)
       if (c < n) D.p[pm_off(D.ai + pos, D.aj + c, D.cn)] = r[c];
   }
   if (info && l == 0) info[b] = inf;
@@ -1702,13 +1702,14 @@ void k_gelqf_big(int m, int n, View C, View D, double *tau, long long sC, long l
 // ---------------------------------------------------------------- gelqf
 // LQ factorization by Householder reflectors of an m-by-n matrix, m, n <= 64
 // (§5.2.2, gelqf; unblocked): one wave per instance with lane i holding row
-// i in 64 registers.  Step k: every lane forms the squared norm of its row
+// i in NC registers (n rounded up to 16).  Step k: every lane forms the squared norm of its row
 // right of column k in ascending column order (the oracle's order; lane k's
 // is the one used), the oracle's scalars follow, lane k scales its row into
 // the reflector, whose entries reach the other lanes by readlane, and every
 // row below forms its product with the reflector and subtracts.  tau goes
 // to dA.  Contraction is off, as in the oracle, so each operation rounds as
 // the oracle's does.  Column k is register 16*qb + kk, selected as in getrf.
+template <int NC>
 __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, double *tau,
                                               long long sC, long long sD, long long stau) {
 #pragma clang fp contract(off)
@@ -1719,15 +1720,15 @@ __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, doub
   const int l = lane_id();
   const bool live = l < m;
   const int lr = min(l, m - 1);
-  double r[64];
+  double r[NC];  // NC: n rounded up to a multiple of 16
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
+  for (int c = 0; c < NC; ++c) {
     const double x = C.p[pm_off(C.ai + lr, C.aj + min(c, n - 1), C.cn)];  // clamped: no branch
     r[c] = (live && c < n) ? x : 0.0;
   }
   const int mn = min(m, n);
 #pragma unroll
-  for (int qb = 0; qb < 4; ++qb) {
+  for (int qb = 0; qb < NC / 16; ++qb) {
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 16 * qb + kk;
       if (k >= mn) break;
@@ -1736,7 +1737,7 @@ __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, doub
       for (int e = 1; e < 16; ++e) rk = kk == e ? r[16 * qb + e] : rk;
       double ss = 0.0;
 #pragma unroll
-      for (int c = 16 * qb; c < 64; ++c)
+      for (int c = 16 * qb; c < NC; ++c)
         if (c < n) ss = c > k ? ss + r[c] * r[c] : ss;
       const double alpha = readlane_d(rk, k);
       const double ssk = readlane_d(ss, k);
@@ -1747,7 +1748,7 @@ __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, doub
         const double sc = 1.0 / (alpha - beta);
         const bool me = l == k;
 #pragma unroll
-        for (int c = 16 * qb; c < 64; ++c)
+        for (int c = 16 * qb; c < NC; ++c)
           if (c < n) r[c] = (me && c > k) ? r[c] * sc : r[c];
 #pragma unroll
         for (int e = 0; e < 16; ++e) r[16 * qb + e] = (me && kk == e) ? beta : r[16 * qb + e];
@@ -1760,11 +1761,11 @@ __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, doub
       const bool below = live && l > k;
       double w = rk;
 #pragma unroll
-      for (int c = 16 * qb; c < 64; ++c)
+      for (int c = 16 * qb; c < NC; ++c)
         if (c < n) w = c > k ? w + r[c] * readlane_d(r[c], k) : w;
       w *= t;
 #pragma unroll
-      for (int c = 16 * qb; c < 64; ++c) {
+      for (int c = 16 * qb; c < NC; ++c) {
         if (c < n) {
           const bool diag = c - 16 * qb == kk;
           const double upd = diag ? r[c] - w : r[c] - w * readlane_d(r[c], k);
@@ -1775,7 +1776,7 @@ __global__ __launch_bounds__(64) void k_gelqf(int m, int n, View C, View D, doub
   }
   if (live) {
 #pragma unroll
-    for (int c = 0; c < 64; ++c)
+    for (int c = 0; c < NC; ++c)
       if (c < n) D.p[pm_off(D.ai + l, D.aj + c, D.cn)] = r[c];
   }
 }
@@ -1795,8 +1796,8 @@ int launch_gelqf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
     hipLaunchKernelGGL(k_gelqf_mf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
                        batch_stride(sC), batch_stride(sD), batch_stride(sD));
   else
-    hipLaunchKernelGGL(k_gelqf, dim3(1, batch), dim3(64), 0, st, m, n, C, D, sD->dA,
-                       batch_stride(sC), batch_stride(sD), batch_stride(sD));
+    hipLaunchKernelGGL(n <= 16 ? k_gelqf<16> : n <= 32 ? k_gelqf<32> : k_gelqf<64>, dim3(1, batch), dim3(64), 0,
+                       st, m, n, C, D, sD->dA, batch_stride(sC), batch_stride(sD), batch_stride(sD));
   return launch_status();
 }
 
@@ -1833,12 +1834,11 @@ int launch_getrf(int batch, int m, int n, const blasfeo_dmat *sC, int ci, int cj
                          info, batch_stride(sC), batch_stride(sD), sdA, sip);
     return launch_status();
   }
-  if (pivot)
-    hipLaunchKernelGGL(k_getrf<true>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
-                       batch_stride(sC), batch_stride(sD), sdA, sip);
-  else
-    hipLaunchKernelGGL(k_getrf<false>, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info,
-                       batch_stride(sC), batch_stride(sD), sdA, sip);
+  // the unblocked kernel, compiled for the column count rounded up to 16
+  auto kern = pivot ? (n <= 16 ? k_getrf<true, 16> : n <= 32 ? k_getrf<true, 32> : k_getrf<true, 64>)
+                    : (n <= 16 ? k_getrf<false, 16> : n <= 32 ? k_getrf<false, 32> : k_getrf<false, 64>);
+  hipLaunchKernelGGL(kern, g, dim3(64), 0, st, m, n, C, D, sD->dA, ipiv, info, batch_stride(sC),
+                     batch_stride(sD), sdA, sip);
   return launch_status();
 }
 
